@@ -1,0 +1,150 @@
+/*
+ * msp.h -- C ABI of libmsp, a GPU (gfx950) solver for the market split
+ * feasibility problem by lattice enumeration.
+ *
+ * Problem (paper, Section 1): given A in Z^{m x n} with entries >= 0 and
+ * d in Z^m, find x in {0,1}^n with A x = d.  The method (Section 2):
+ *   1. embed the problem in the lattice spanned by the n+1 columns of the
+ *      (m+n+1) x (n+1) matrix of eq. (2), binary case r_max = c_i = 1,
+ *      with a scale constant N (default 2^10);
+ *   2. LLL-reduce that basis (step 1 of Algorithm 1) and keep the n-m+1
+ *      reduced vectors whose first m entries vanish, dropping those entries
+ *      (step 2) -- a basis b_0..b_{n-m} of the kernel lattice in Z^{n+1};
+ *   3. Gram-Schmidt orthogonalise it (eq. (4), step 3);
+ *   4. enumerate depth first every lattice vector v with ||v||_2^2 <= n+1
+ *      that passes the Hoelder test of Thm 2 (Algorithm 1), and read the
+ *      solutions off the vectors with ||v||_inf <= 1 (Thm 1).
+ *
+ * Conventions shared by every call:
+ *   - Matrices are row-major.  A is int32 m x n; d is int64 m.
+ *   - A kernel basis is int64 k x (n+1), k = n - m + 1, one basis vector per
+ *     row; columns 0..n-1 are the variable coordinates (v_j = 2 x_j - 1 on
+ *     a solution) and column n is the r_max coordinate (|v_n| = 1 on a
+ *     solution).
+ *   - Pointers named *_dev are device pointers on the context's device;
+ *     all other pointers are host pointers.  The caller allocates and frees
+ *     every buffer it passes.  The library never frees caller memory and
+ *     keeps no caller pointer after a call returns: every call synchronises
+ *     `stream` before returning.
+ *   - `stream` is a hipStream_t (NULL = the null stream).
+ *   - Every call returns MSP_OK (0) or a negative MSP_E_* code and never
+ *     aborts or throws across the ABI.  msp_strerror() names a code.
+ *   - A context is not thread safe: use one context per host thread.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+    MSP_OK = 0,
+    MSP_E_ARG = -1,          /* bad shape, null pointer, m > n, n > MSP_MAX_N     */
+    MSP_E_RANK = -2,         /* fewer than n-m+1 kernel vectors: rank A < m        */
+    MSP_E_NOT_ISOLATED = -3, /* N too small: reduced basis does not split (Sec. 2) */
+    MSP_E_OVERFLOW = -4,     /* an integer bound was exceeded (see each call)      */
+    MSP_E_CAPACITY = -5,     /* more solutions than `cap`; *n_found = true total   */
+    MSP_E_TIMEOUT = -6,      /* time cap hit; partial results are valid            */
+    MSP_E_DEVICE = -7,       /* a HIP runtime error                                */
+    MSP_E_NOMEM = -8,        /* device allocation failed                           */
+    MSP_E_UNSUPPORTED = -9,  /* shape outside the compiled kernel variants         */
+    MSP_E_NUMERIC = -10      /* floating-point breakdown (non-positive GS norm)    */
+};
+
+#define MSP_MAX_N 127        /* largest n accepted (n + 1 <= 128)                */
+
+/* enumeration modes */
+enum { MSP_ALL = 0, MSP_FIRST = 1 };
+/* subtree root orders for MSP_FIRST (MSP_ALL ignores the order) */
+enum { MSP_PLAIN = 0, MSP_LEARNED = 1 };
+
+typedef struct msp_ctx msp_ctx;
+
+/* Tunables.  msp_params_default() fills the defaults given in brackets. */
+typedef struct {
+    int64_t N;            /* scale constant of eq. (2)                       [1024] */
+    double delta;         /* LLL Lovász parameter                            [0.99] */
+    double eps;           /* relative slack of both pruning tests            [1e-9] */
+    int split_depth;      /* levels enumerated before the subtree split; -1 = auto [-1] */
+    int block;            /* threads per workgroup of the walk kernel; 0 = auto  [0] */
+    int target_roots;     /* root count the automatic split aims for; 0 = auto  [0] */
+    int hoelder;          /* 1: apply the Hoelder test (Thm 2)                  [1] */
+    int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
+    double time_cap_ms;   /* enumeration wall-time cap; <= 0 = none             [0] */
+} msp_params;
+
+/* Counters and timings of one call (all times in milliseconds).
+ * eval = a candidate u_t whose partial norm was computed; node = a candidate
+ * that passed the l2 test; expansion = a node that passed the Hoelder test and
+ * was descended into; leaf = a node at level 0. */
+typedef struct {
+    int64_t evals, nodes, expansions, leaves;
+    int64_t roots;           /* subtree roots in the queue                       */
+    int32_t split_depth;     /* split depth used                                 */
+    int32_t k;               /* kernel lattice rank n - m + 1                    */
+    double reduce_ms;        /* msp_reduce (embedding + LLL + extraction)        */
+    double gs_ms;            /* Gram-Schmidt kernel                              */
+    double rootgen_ms;       /* root generation (levels above the split)         */
+    double ordering_ms;      /* root scoring and sort (learned order only)       */
+    double kernel_ms;        /* walk kernel                                      */
+    double ttfs_ms;          /* MSP_FIRST: walk-kernel start to first verified hit; -1 if none */
+    double total_ms;         /* whole call                                       */
+} msp_stats;
+
+/* Fill `p` with the defaults.  Returns MSP_OK or MSP_E_ARG (p == NULL). */
+int msp_params_default(msp_params *p);
+
+/* Create a context bound to HIP device `device`.  The context owns its
+ * workspace (root queue, walker stacks, counters, model weights), grown on
+ * demand and freed by msp_ctx_destroy. */
+int msp_ctx_create(int device, msp_ctx **out);
+void msp_ctx_destroy(msp_ctx *ctx);
+
+/* Steps 1-2 of Algorithm 1 on the GPU (Section 2, eq. (2)).
+ * Builds the embedding basis with scale p->N, LLL-reduces it in FP64 with
+ * exact int64 basis updates (Lovász p->delta), keeps the reduced vectors whose
+ * first m entries are zero and writes them, top entries dropped, to
+ * basis_dev (int64 k x (n+1), capacity (n+1) x (n+1)); *k_out = k = n-m+1.
+ * Errors: MSP_E_ARG, MSP_E_NOT_ISOLATED (other than k zero-top vectors),
+ * MSP_E_OVERFLOW (an int64 entry or Gram entry beyond 2^53),
+ * MSP_E_NUMERIC (LLL failed to converge), MSP_E_DEVICE. */
+int msp_reduce(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+               const msp_params *p, int64_t *basis_dev, int *k_out, void *stream);
+
+/* Step 3 of Algorithm 1 (eq. (4)): FP64 Gram-Schmidt of a kernel basis.
+ * basis_dev: int64 k x dim.  Outputs (device, caller-allocated):
+ * bhat_dev k x dim (row i = b_hat_i), mu_dev k x k (mu_dev[i*k+j] = mu_ij for
+ * j < i, 1 on the diagonal, 0 above), beta_dev k (||b_hat_i||^2).
+ * Errors: MSP_E_ARG, MSP_E_NUMERIC (some beta_i <= 0: dependent basis). */
+int msp_gram_schmidt(msp_ctx *ctx, int k, int dim, const int64_t *basis_dev,
+                     double *bhat_dev, double *mu_dev, double *beta_dev, void *stream);
+
+/* Step 3-4 of Algorithm 1 on a given kernel basis: Gram-Schmidt, root
+ * generation above the split depth, and the subtree walk (Algorithm 1 with
+ * the zig-zag order of next(), the l2 bound R = n+1, the Hoelder test and the
+ * one-direction cut), with an exact check of every level-0 node (Thm 1, then
+ * A x = d in integers).
+ * mode MSP_ALL returns every solution exactly once (unspecified order);
+ * MSP_FIRST stops at the first verified solution (one or a few rows).
+ * order: MSP_PLAIN (depth-first root order) or MSP_LEARNED (roots sorted by
+ * the context's root-scoring model; needs msp_set_order_model first).
+ * x_dev: uint8 cap x n, rows of 0/1.  *n_found: solutions found (may exceed
+ * cap: then only cap rows are written and MSP_E_CAPACITY is returned after the
+ * full enumeration).  stats may be NULL.
+ * Errors: MSP_E_ARG, MSP_E_UNSUPPORTED, MSP_E_OVERFLOW (|u_t| > 127 reached),
+ * MSP_E_CAPACITY, MSP_E_TIMEOUT, MSP_E_NOMEM, MSP_E_DEVICE. */
+int msp_enumerate(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                  const int64_t *basis_dev, int k, int mode, int order, const msp_params *p,
+                  uint8_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *msp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

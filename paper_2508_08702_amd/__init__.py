@@ -1,0 +1,241 @@
+"""GPU (gfx950) market split solver by lattice enumeration -- Python binding.
+
+A thin ctypes layer over ``libmsp.so`` (C ABI in ``include/msp.h``).  The
+functions below carry the C names and only marshal arguments: PyTorch
+tensors supply device memory and the current HIP stream, and every step of
+the method runs in the library's kernels.  There is no CPU fallback: if the
+library is missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsp.so")
+
+MSP_OK = 0
+MSP_E_ARG = -1
+MSP_E_RANK = -2
+MSP_E_NOT_ISOLATED = -3
+MSP_E_OVERFLOW = -4
+MSP_E_CAPACITY = -5
+MSP_E_TIMEOUT = -6
+MSP_E_DEVICE = -7
+MSP_E_NOMEM = -8
+MSP_E_UNSUPPORTED = -9
+MSP_E_NUMERIC = -10
+
+MSP_ALL = 0
+MSP_FIRST = 1
+MSP_PLAIN = 0
+MSP_LEARNED = 1
+MSP_MAX_N = 127
+
+# every symbol include/msp.h declares
+EXPORTED = (
+    "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
+    "msp_gram_schmidt", "msp_enumerate", "msp_strerror",
+)
+
+
+class MspError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {msp_strerror(code)} ({code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("N", C.c_int64), ("delta", C.c_double), ("eps", C.c_double),
+        ("split_depth", C.c_int), ("block", C.c_int), ("target_roots", C.c_int),
+        ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("evals", C.c_int64), ("nodes", C.c_int64), ("expansions", C.c_int64), ("leaves", C.c_int64),
+        ("roots", C.c_int64), ("split_depth", C.c_int32), ("k", C.c_int32),
+        ("reduce_ms", C.c_double), ("gs_ms", C.c_double), ("rootgen_ms", C.c_double),
+        ("ordering_ms", C.c_double), ("kernel_ms", C.c_double), ("ttfs_ms", C.c_double),
+        ("total_ms", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_08702_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+    lib.msp_params_default.argtypes = [C.POINTER(Params)]
+    lib.msp_params_default.restype = i32
+    lib.msp_ctx_create.argtypes = [i32, C.POINTER(vp)]
+    lib.msp_ctx_create.restype = i32
+    lib.msp_ctx_destroy.argtypes = [vp]
+    lib.msp_ctx_destroy.restype = None
+    lib.msp_reduce.argtypes = [vp, i32, i32, vp, vp, C.POINTER(Params), vp, C.POINTER(i32), vp]
+    lib.msp_reduce.restype = i32
+    lib.msp_gram_schmidt.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.msp_gram_schmidt.restype = i32
+    lib.msp_enumerate.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, i64,
+                                  C.POINTER(i64), C.POINTER(Stats), vp]
+    lib.msp_enumerate.restype = i32
+    lib.msp_strerror.argtypes = [i32]
+    lib.msp_strerror.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def msp_strerror(code: int) -> str:
+    return _lib.msp_strerror(int(code)).decode()
+
+
+def msp_params_default(**overrides) -> Params:
+    p = Params()
+    rc = _lib.msp_params_default(C.byref(p))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_params_default")
+    for key, val in overrides.items():
+        if not hasattr(p, key):
+            raise KeyError(key)
+        setattr(p, key, val)
+    return p
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, device: torch.device, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    return t.data_ptr()
+
+
+class Context:
+    """Owns an ``msp_ctx`` (device workspace) for one device."""
+
+    def __init__(self, device: int | torch.device = 0):
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("Context needs a GPU device")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else 0)
+        h = C.c_void_p()
+        rc = _lib.msp_ctx_create(self.device.index, C.byref(h))
+        if rc != MSP_OK:
+            raise MspError(rc, "msp_ctx_create")
+        self._h = h
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise RuntimeError("context destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.msp_ctx_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def msp_ctx_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def msp_ctx_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def msp_gram_schmidt(ctx: Context, basis: torch.Tensor):
+    """FP64 Gram-Schmidt of a kernel basis (int64 k x dim on the device).
+    Returns (bhat k x dim, mu k x k, beta k) as float64 device tensors."""
+    k, dim = basis.shape
+    dev = ctx.device
+    bp = _dev_ptr(basis, torch.int64, dev, "basis")
+    bhat = torch.empty((k, dim), dtype=torch.float64, device=dev)
+    mu = torch.empty((k, k), dtype=torch.float64, device=dev)
+    beta = torch.empty((k,), dtype=torch.float64, device=dev)
+    rc = _lib.msp_gram_schmidt(ctx.handle, k, dim, bp, bhat.data_ptr(), mu.data_ptr(), beta.data_ptr(),
+                               _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_gram_schmidt")
+    return bhat, mu, beta
+
+
+def msp_reduce(ctx: Context, A: torch.Tensor, d: torch.Tensor, params: Params | None = None):
+    """Embedding + LLL + kernel extraction on the GPU.  Returns the int64
+    kernel basis (k x (n+1)) as a device tensor."""
+    m, n = A.shape
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    basis = torch.zeros((n + 1, n + 1), dtype=torch.int64, device=dev)
+    k = C.c_int(0)
+    p = params if params is not None else msp_params_default()
+    rc = _lib.msp_reduce(ctx.handle, m, n, ap, dp, C.byref(p), basis.data_ptr(), C.byref(k), _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_reduce")
+    return basis[: k.value].contiguous()
+
+
+@dataclass
+class EnumResult:
+    x: torch.Tensor       # uint8 (rows, n) on the device, rows = min(n_found, cap)
+    n_found: int
+    status: int
+    stats: dict
+
+
+def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.Tensor, *,
+                  mode: int = MSP_ALL, order: int = MSP_PLAIN, params: Params | None = None,
+                  cap: int = 1 << 16, out: torch.Tensor | None = None,
+                  raise_on_error: bool = True) -> EnumResult:
+    """Enumerate the solutions of A x = d on a given kernel basis.
+
+    MSP_CAPACITY and MSP_TIMEOUT are reported in ``status`` (rows written are
+    valid); other errors raise unless ``raise_on_error`` is False."""
+    m, n = A.shape
+    k = basis.shape[0]
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    bp = _dev_ptr(basis, torch.int64, dev, "basis")
+    if out is None:
+        out = torch.zeros((max(cap, 1), n), dtype=torch.uint8, device=dev)
+    else:
+        _dev_ptr(out, torch.uint8, dev, "out")
+        cap = min(cap, out.shape[0])
+    p = params if params is not None else msp_params_default()
+    nf = C.c_int64(0)
+    st = Stats()
+    rc = _lib.msp_enumerate(ctx.handle, m, n, ap, dp, bp, k, int(mode), int(order), C.byref(p),
+                            out.data_ptr(), int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
+    if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
+        raise MspError(rc, "msp_enumerate")
+    rows = min(nf.value, cap)
+    return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())

@@ -1,0 +1,404 @@
+// C ABI of libmsp (declared in include/msp.h): argument checks, the
+// context's device workspace, and the sequence of kernel launches for each
+// call.  No arithmetic of the method happens on the host: every step runs in
+// the kernels of gs.hip, rootgen.hip, walk.hip and lll.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/msp.h"
+#include "msp_internal.h"
+
+using namespace msp;
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        size_t nb = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, nb);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = nb;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T>
+    T *as() const {
+        return reinterpret_cast<T *>(p);
+    }
+};
+
+struct FrontierBuf {
+    Buf u, w, l, tz;
+    int64_t cap = 0;
+    hipError_t ensure(int64_t n, int k, int ws) {
+        hipError_t e;
+        if ((e = u.ensure((size_t)n * k)) != hipSuccess) return e;
+        if ((e = w.ensure((size_t)n * ws * sizeof(double))) != hipSuccess) return e;
+        if ((e = l.ensure((size_t)n * sizeof(double))) != hipSuccess) return e;
+        if ((e = tz.ensure((size_t)n)) != hipSuccess) return e;
+        cap = n;
+        return hipSuccess;
+    }
+    Frontier view() const { return Frontier{u.as<int8_t>(), w.as<double>(), l.as<double>(), tz.as<uint8_t>()}; }
+    void release() {
+        u.release();
+        w.release();
+        l.release();
+        tz.release();
+        cap = 0;
+    }
+};
+
+// Small device-side control block, one allocation.
+struct Ctl {
+    unsigned long long counters[8];  // evals nodes expansions leaves roots
+    unsigned long long qhead;
+    unsigned long long n_found;
+    unsigned long long t_first;
+    unsigned long long t_start;
+    int flags[8];                    // stop overflow timeout internal
+    int gs_err;
+    int pad;
+    int64_t total;
+};
+
+}  // namespace
+
+struct msp_ctx {
+    int device = 0;
+    int num_cus = 0;
+    double wall_khz = 100000.0;
+    Buf gs_bhat, gs_mu, gs_beta;
+    FrontierBuf fr[2];
+    Buf counts, offs;
+    Buf stack;
+    Buf ctl;
+    Buf order;
+    hipEvent_t ev[8] = {};
+};
+
+namespace {
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return MSP_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MSP_E_NOMEM;
+    return MSP_E_DEVICE;
+}
+
+#define MSP_TRY(expr)                          \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return map_err(_e); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msp_params_default(msp_params *p) {
+    if (!p) return MSP_E_ARG;
+    p->N = 1024;
+    p->delta = 0.99;
+    p->eps = 1e-9;
+    p->split_depth = -1;
+    p->block = 0;
+    p->target_roots = 0;
+    p->hoelder = 1;
+    p->onedir = 1;
+    p->time_cap_ms = 0.0;
+    return MSP_OK;
+}
+
+const char *msp_strerror(int code) {
+    switch (code) {
+        case MSP_OK: return "ok";
+        case MSP_E_ARG: return "invalid argument";
+        case MSP_E_RANK: return "rank of A is below m";
+        case MSP_E_NOT_ISOLATED: return "scale N too small: kernel vectors not isolated";
+        case MSP_E_OVERFLOW: return "integer bound exceeded";
+        case MSP_E_CAPACITY: return "more solutions than the output capacity";
+        case MSP_E_TIMEOUT: return "time cap reached";
+        case MSP_E_DEVICE: return "HIP runtime error";
+        case MSP_E_NOMEM: return "device memory allocation failed";
+        case MSP_E_UNSUPPORTED: return "shape outside the compiled kernel variants";
+        case MSP_E_NUMERIC: return "floating-point breakdown";
+        default: return "unknown status";
+    }
+}
+
+int msp_ctx_create(int device, msp_ctx **out) {
+    if (!out) return MSP_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MSP_E_DEVICE;
+    DeviceGuard g(device);
+    msp_ctx *c = new (std::nothrow) msp_ctx();
+    if (!c) return MSP_E_NOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return MSP_E_DEVICE;
+    }
+    c->num_cus = prop.multiProcessorCount;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
+        c->wall_khz = rate;
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            msp_ctx_destroy(c);
+            return MSP_E_DEVICE;
+        }
+    }
+    if (c->ctl.ensure(sizeof(Ctl)) != hipSuccess) {
+        msp_ctx_destroy(c);
+        return MSP_E_NOMEM;
+    }
+    *out = c;
+    return MSP_OK;
+}
+
+void msp_ctx_destroy(msp_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    c->gs_bhat.release();
+    c->gs_mu.release();
+    c->gs_beta.release();
+    c->fr[0].release();
+    c->fr[1].release();
+    c->counts.release();
+    c->offs.release();
+    c->stack.release();
+    c->ctl.release();
+    c->order.release();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int msp_gram_schmidt(msp_ctx *c, int k, int dim, const int64_t *basis_dev, double *bhat_dev, double *mu_dev,
+                     double *beta_dev, void *stream) {
+    if (!c || !basis_dev || !bhat_dev || !mu_dev || !beta_dev) return MSP_E_ARG;
+    if (k < 1 || dim < 1 || k > dim || dim > MSP_MAX_N + 1) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    Ctl *ctl = c->ctl.as<Ctl>();
+    MSP_TRY(hipMemsetAsync(&ctl->gs_err, 0, sizeof(int), st));
+    GsArgs a{k, dim, basis_dev, bhat_dev, mu_dev, beta_dev, &ctl->gs_err};
+    MSP_TRY(launch_gram_schmidt(a, st));
+    int err = 0;
+    MSP_TRY(hipMemcpyAsync(&err, &ctl->gs_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    return err ? MSP_E_NUMERIC : MSP_OK;
+}
+
+int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
+                  int k, int mode, int order, const msp_params *pin, uint8_t *x_dev, int64_t cap, int64_t *n_found,
+                  msp_stats *stats, void *stream) {
+    auto t_call = std::chrono::steady_clock::now();
+    if (!c || !A_dev || !d_dev || !basis_dev || !n_found || (cap > 0 && !x_dev) || cap < 0) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N || k != n - m + 1) return MSP_E_ARG;
+    if (mode != MSP_ALL && mode != MSP_FIRST) return MSP_E_ARG;
+    if (order != MSP_PLAIN) return MSP_E_UNSUPPORTED;
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (!(p.eps >= 0.0) || p.split_depth < -1 || p.split_depth > k - 1) return MSP_E_ARG;
+    *n_found = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = n + 1;
+    const int dimp = dimp_for(dim);
+    if (dimp < 0) return MSP_E_UNSUPPORTED;
+    const int ws = dimp + kWsTail;
+    const int block = 256;
+    if (p.block != 0 && p.block != block) return MSP_E_UNSUPPORTED;
+
+    // ---- Gram-Schmidt (step 3) ----
+    MSP_TRY(c->gs_bhat.ensure((size_t)k * dim * sizeof(double)));
+    MSP_TRY(c->gs_mu.ensure((size_t)k * k * sizeof(double)));
+    MSP_TRY(c->gs_beta.ensure((size_t)k * sizeof(double)));
+    Ctl *ctl = c->ctl.as<Ctl>();
+    MSP_TRY(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    MSP_TRY(hipEventRecord(c->ev[0], st));
+    GsArgs ga{k, dim, basis_dev, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->gs_beta.as<double>(),
+              &ctl->gs_err};
+    MSP_TRY(launch_gram_schmidt(ga, st));
+    MSP_TRY(hipEventRecord(c->ev[1], st));
+    int gs_err = 0;
+    MSP_TRY(hipMemcpyAsync(&gs_err, &ctl->gs_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    if (gs_err) return MSP_E_NUMERIC;
+
+    const double R = (double)(n + 1);  // (n+1) r_max^2, r_max = 1 (Algorithm 1, step 4)
+    const double bound = R * (1.0 + p.eps);
+    const double hfac = 1.0 + p.eps;
+
+    // ---- root generation: levels k-1 .. L breadth first ----
+    const int per_cu_max = 2;
+    const int64_t walkers = (int64_t)c->num_cus * per_cu_max * block;
+    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(8 * walkers, 4096);
+    const int64_t fcap = std::max<int64_t>(4 * target, 1 << 16);
+    MSP_TRY(c->fr[0].ensure(fcap, k, ws));
+    MSP_TRY(c->fr[1].ensure(fcap, k, ws));
+    MSP_TRY(c->counts.ensure((size_t)fcap * sizeof(int64_t)));
+    MSP_TRY(c->offs.ensure((size_t)fcap * sizeof(int64_t)));
+    MSP_TRY(hipEventRecord(c->ev[2], st));
+    MSP_TRY(launch_frontier_init(c->fr[0].view(), k, ws, st));
+    int cur = 0;
+    int64_t np = 1;
+    int L = k;
+    const bool fixed = p.split_depth >= 0;
+    for (int t = k - 1; t >= 1; --t) {
+        if (fixed && k - L >= p.split_depth) break;
+        if (!fixed && np >= target) break;
+        ExpandArgs ea{};
+        ea.k = k;
+        ea.dim = dim;
+        ea.dimp = dimp;
+        ea.ws = ws;
+        ea.t = t;
+        ea.bhat = c->gs_bhat.as<double>();
+        ea.mu = c->gs_mu.as<double>();
+        ea.beta = c->gs_beta.as<double>();
+        ea.par = c->fr[cur].view();
+        ea.np = np;
+        ea.ch = c->fr[cur ^ 1].view();
+        ea.offs = c->offs.as<int64_t>();
+        ea.counts = c->counts.as<int64_t>();
+        ea.bound = bound;
+        ea.hfac = hfac;
+        ea.hoelder = p.hoelder;
+        ea.onedir = p.onedir;
+        ea.counters = ctl->counters;
+        ea.flags = ctl->flags;
+        MSP_TRY(launch_expand_count(ea, st));
+        MSP_TRY(launch_scan(c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total, st));
+        int64_t total = 0;
+        MSP_TRY(hipMemcpyAsync(&total, &ctl->total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MSP_TRY(hipStreamSynchronize(st));
+        if (total > fcap) break;  // cannot hold this level: split above it
+        MSP_TRY(launch_expand_write(ea, st));
+        cur ^= 1;
+        np = total;
+        L = t;
+        if (np == 0) break;
+    }
+    MSP_TRY(hipEventRecord(c->ev[3], st));
+
+    // ---- subtree walk (levels L-1 .. 0) ----
+    const size_t lds = walk_lds_bytes(dimp, block, k, L);
+    if (lds > 160 * 1024) return MSP_E_UNSUPPORTED;
+    MSP_TRY(c->stack.ensure((size_t)walkers * k * 4 * sizeof(double)));
+    if (np > 0) {
+        WalkArgs wa{};
+        wa.k = k;
+        wa.dim = dim;
+        wa.n = n;
+        wa.m = m;
+        wa.L = L;
+        wa.bhat = c->gs_bhat.as<double>();
+        wa.mu = c->gs_mu.as<double>();
+        wa.beta = c->gs_beta.as<double>();
+        wa.basis = basis_dev;
+        wa.A = A_dev;
+        wa.d = d_dev;
+        wa.roots = c->fr[cur].view();
+        wa.nroots = np;
+        wa.order = nullptr;
+        wa.qhead = &ctl->qhead;
+        wa.stack = c->stack.as<double>();
+        wa.x_out = x_dev;
+        wa.cap = cap;
+        wa.n_found = &ctl->n_found;
+        wa.counters = ctl->counters;
+        wa.flags = ctl->flags;
+        wa.t_first = &ctl->t_first;
+        wa.t_start = &ctl->t_start;
+        wa.deadline = p.time_cap_ms > 0 ? (unsigned long long)(p.time_cap_ms * c->wall_khz) : 0ull;
+        wa.mode = mode;
+        wa.bound = bound;
+        wa.hfac = hfac;
+        wa.hoelder = p.hoelder;
+        wa.onedir = p.onedir;
+        MSP_TRY(hipEventRecord(c->ev[4], st));
+        MSP_TRY(launch_walk(wa, dimp, block, c->num_cus, st));
+        MSP_TRY(hipEventRecord(c->ev[5], st));
+    } else {
+        MSP_TRY(hipEventRecord(c->ev[4], st));
+        MSP_TRY(hipEventRecord(c->ev[5], st));
+    }
+    Ctl h;
+    MSP_TRY(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+
+    *n_found = (int64_t)h.n_found;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->evals = (int64_t)h.counters[0];
+        stats->nodes = (int64_t)h.counters[1];
+        stats->expansions = (int64_t)h.counters[2];
+        stats->leaves = (int64_t)h.counters[3];
+        stats->roots = np;
+        stats->split_depth = k - L;
+        stats->k = k;
+        stats->gs_ms = elapsed(c->ev[0], c->ev[1]);
+        stats->rootgen_ms = elapsed(c->ev[2], c->ev[3]);
+        stats->kernel_ms = elapsed(c->ev[4], c->ev[5]);
+        stats->ttfs_ms = (h.t_first && h.t_start) ? (double)(h.t_first - h.t_start) / c->wall_khz : -1.0;
+        stats->total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+    }
+    if (h.flags[3]) return MSP_E_NUMERIC;
+    if (h.flags[1]) return MSP_E_OVERFLOW;
+    if (h.flags[2]) return MSP_E_TIMEOUT;
+    if ((int64_t)h.n_found > cap) return MSP_E_CAPACITY;
+    return MSP_OK;
+}
+
+int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *p,
+               int64_t *basis_dev, int *k_out, void *stream) {
+    (void)c; (void)m; (void)n; (void)A_dev; (void)d_dev; (void)p; (void)basis_dev; (void)k_out; (void)stream;
+    return MSP_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP translation units of libmsp.
+// Every kernel is launched from a host wrapper in the file that defines it;
+// the wrappers below are what the C ABI layer (api.hip) calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msp {
+
+// Root / frontier record layout (structure of arrays, one entry per record):
+//   u   int8  [cap x k]   prefix u_i for levels >= the record's level, 0 below
+//   w   f64   [cap x WS]  projected vector w^(level) in natural column order,
+//                         zero padded to DIMP columns, then a copy of columns
+//                         0..WS-DIMP-1 (so that a lane rotated by r can read
+//                         w[r .. r+DIMP) without wrapping)
+//   l   f64   [cap]       ||w||^2 by the partial-norm recurrence
+//   tz  uint8 [cap]       1 while every u above the record's level is zero
+struct Frontier {
+    int8_t *u;
+    double *w;
+    double *l;
+    uint8_t *tz;
+};
+
+// Width of the padded projected vector held per lane, and of records.
+constexpr int kRotMax = 14;   // largest lane rotation (columns), see walk.hip
+constexpr int kWsTail = 16;   // WS = DIMP + kWsTail
+
+inline int dimp_for(int dim) {
+    // supported compile-time widths (even, ascending)
+    static const int widths[] = {24, 32, 40, 48, 52, 56, 64, 72, 82, 88, 96, 102, 112, 128};
+    for (int w : widths)
+        if (dim <= w) return w;
+    return -1;
+}
+
+struct GsArgs {
+    int k, dim;
+    const int64_t *basis;   // k x dim
+    double *bhat;           // k x dim
+    double *mu;             // k x k
+    double *beta;           // k
+    int *err;               // set to 1 on a non-positive norm
+};
+hipError_t launch_gram_schmidt(const GsArgs &a, hipStream_t st);
+
+struct ExpandArgs {
+    int k, dim, dimp, ws, t;       // t: level whose candidates are enumerated
+    const double *bhat, *mu, *beta;
+    Frontier par;                  // parents: expanded nodes of level t+1
+    int64_t np;
+    Frontier ch;                   // children (write pass only)
+    const int64_t *offs;           // write pass: first child slot per parent
+    int64_t *counts;               // count pass: children per parent
+    double bound, hfac;
+    int hoelder, onedir;
+    unsigned long long *counters;  // [0] evals [1] nodes [2] expansions (write pass)
+    int *flags;                    // [1] |u| > 127 seen
+};
+hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st);
+hipError_t launch_expand_write(const ExpandArgs &a, hipStream_t st);
+hipError_t launch_frontier_init(Frontier f, int k, int ws, hipStream_t st);
+// exclusive prefix sum of counts[0..n) into offs, total into *total
+hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t *total, hipStream_t st);
+
+struct WalkArgs {
+    int k, dim, n, m, L;           // L: level of the roots; walkers live on levels < L
+    const double *bhat, *mu, *beta;
+    const int64_t *basis;          // k x dim, exact leaf reconstruction
+    const int32_t *A;
+    const int64_t *d;
+    Frontier roots;
+    int64_t nroots;
+    const int64_t *order;          // optional permutation of roots (nullptr = identity)
+    unsigned long long *qhead;     // next root index
+    double *stack;                 // per walker k entries x 4 doubles
+    uint8_t *x_out;
+    int64_t cap;
+    unsigned long long *n_found;
+    unsigned long long *counters;  // [0] evals [1] nodes [2] expansions [3] leaves [4] roots done
+    int *flags;                    // [0] stop [1] overflow [2] timeout [3] internal error
+    unsigned long long *t_first;   // wall clock of the first verified hit (0 = none)
+    unsigned long long *t_start;   // wall clock when the kernel started
+    unsigned long long deadline;   // time cap in wall-clock ticks from kernel start (0 = none)
+    int mode;                      // 0 all, 1 first
+    double bound, hfac;
+    int hoelder, onedir;
+};
+// Returns hipErrorInvalidValue when no compiled variant fits (dim, k, L).
+hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);
+size_t walk_lds_bytes(int dimp, int block, int k, int L);
+
+}  // namespace msp

@@ -1,0 +1,152 @@
+// Subtree root generation: the top levels of the enumeration tree, expanded
+// breadth first, one level per launch (tree partitioning, paper Section 4).
+//
+// A level-t launch takes the expanded nodes of level t+1 ("parents", each with
+// its prefix u_{t+1..k-1}, projected vector w^(t+1) and partial norm) and, one
+// thread per parent, runs the level-t rules of Algorithm 1: zig-zag values
+// around the centre, the l2 bound, the Hoelder test and the one-direction
+// cut.  Every candidate that passes both tests is an expanded node of level t.
+// A count pass, an exclusive scan and a write pass store the children of
+// parent p contiguously after those of parent p-1, each parent's children in
+// zig-zag order -- so every level of the frontier is in depth-first order, and
+// the last frontier is the root queue in the order sequential DFS meets it.
+#include "enum_rules.h"
+#include "msp_internal.h"
+
+namespace msp {
+
+template <bool WRITE>
+__global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long ce = 0, cn = 0, cx = 0;
+    if (p < a.np) {
+        const int k = a.k, dim = a.dim, t = a.t, ws = a.ws;
+        const int8_t *up = a.par.u + p * k;
+        const double *wp = a.par.w + p * ws;
+        const double lpar = a.par.l[p];
+        const bool tz = a.par.tz[p] != 0;
+        double y = 0.0;
+        for (int i = k - 1; i > t; --i) y = add_rn(y, mul_rn((double)up[i], a.mu[(size_t)i * k + t]));
+        const Zig z = zig_init(y, tz);
+        int u = z.u1;
+        bool onedir = tz;
+        int dir = 1;
+        const double beta = a.beta[t];
+        const double *bt = a.bhat + (size_t)t * dim;
+        int64_t slot = WRITE ? a.offs[p] : 0;
+        int64_t nch = 0;
+        for (;;) {
+            const double x = add_rn((double)u, y);
+            const double l = partial_norm(x, beta, lpar);
+            ++ce;
+            if (!(l <= a.bound)) break;  // NaN ends the level too
+            ++cn;
+            bool fail = false;
+            if (a.hoelder) {
+                double h = 0.0;
+                for (int j = 0; j < dim; ++j) h += fabs(fma(x, bt[j], wp[j]));
+                fail = l > h * a.hfac;
+            }
+            if (fail) {
+                if (a.onedir) {
+                    if (onedir) break;
+                    u = zig_next(z, u);
+                    onedir = true;
+                    dir = side_of(u, y);
+                    continue;
+                }
+            } else {
+                ++cx;
+                if (WRITE) {
+                    if (u > 127 || u < -127) atomicOr(&a.flags[1], 1);
+                    int8_t *uc = a.ch.u + slot * k;
+                    for (int i = 0; i < k; ++i) uc[i] = i > t ? up[i] : (i == t ? (int8_t)u : (int8_t)0);
+                    double *wc = a.ch.w + slot * ws;
+                    for (int j = 0; j < a.dimp; ++j) wc[j] = j < dim ? fma(x, bt[j], wp[j]) : 0.0;
+                    for (int j = a.dimp; j < ws; ++j) wc[j] = wc[j - a.dimp];
+                    a.ch.l[slot] = l;
+                    a.ch.tz[slot] = (tz && u == 0) ? 1 : 0;
+                    ++slot;
+                }
+                ++nch;
+            }
+            u = onedir ? u + dir : zig_next(z, u);
+        }
+        if (!WRITE) a.counts[p] = nch;
+    }
+    if (WRITE) {
+        // wave reduction, one atomic per wave
+        for (int o = 32; o >= 1; o >>= 1) {
+            ce += __shfl_xor(ce, o, 64);
+            cn += __shfl_xor(cn, o, 64);
+            cx += __shfl_xor(cx, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && (ce | cn | cx)) {
+            atomicAdd(&a.counters[0], ce);
+            atomicAdd(&a.counters[1], cn);
+            atomicAdd(&a.counters[2], cx);
+        }
+    }
+}
+
+__global__ void frontier_init_kernel(Frontier f, int k, int ws) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) f.u[i] = 0;
+    for (int j = threadIdx.x; j < ws; j += blockDim.x) f.w[j] = 0.0;
+    if (threadIdx.x == 0) {
+        f.l[0] = 0.0;
+        f.tz[0] = 1;
+    }
+}
+
+// Exclusive scan by one 1024-thread workgroup: thread i sums a contiguous
+// segment, the segment sums are scanned in LDS, and each thread writes its
+// segment's offsets.
+__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *counts, int64_t *offs, int64_t n,
+                                                    int64_t *total) {
+    __shared__ int64_t part[1024];
+    const int64_t seg = (n + 1023) / 1024;
+    const int64_t lo = (int64_t)threadIdx.x * seg;
+    const int64_t hi = lo + seg < n ? lo + seg : n;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        offs[i] = run;
+        run += counts[i];
+    }
+    if (threadIdx.x == 1023) *total = part[1023];
+}
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st) {
+    if (a.np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(expand_kernel<false>, dim3(grid_for(a.np)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_write(const ExpandArgs &a, hipStream_t st) {
+    if (a.np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(expand_kernel<true>, dim3(grid_for(a.np)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontier_init(Frontier f, int k, int ws, hipStream_t st) {
+    hipLaunchKernelGGL(frontier_init_kernel, dim3(1), dim3(256), 0, st, f, k, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t *total, hipStream_t st) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, counts, offs, n, total);
+    return hipGetLastError();
+}
+
+}  // namespace msp
