@@ -1,0 +1,177 @@
+"""Benchmark: lattice enumeration for market split instances on one MI355X.
+
+One step = the whole GPU path for every instance of the workload: embedding +
+LLL + kernel extraction (msp_reduce), Gram-Schmidt, root generation and the
+exhaustive subtree walk (msp_enumerate, mode all).  Inputs (A, d) are resident
+on the device before timing starts.  The headline value is enumeration nodes
+per second over the whole step (a node is a candidate that passed the l2
+test), i.e. total nodes / wall time of the step.
+
+Also reported:
+  roofline      the walk kernel against FP64 vector peak: algorithmic flops
+                per node 3 (n+1) + 4 (an axpy and an l1 norm over n+1
+                coordinates plus the partial-norm recurrence) and 4 per
+                candidate that fails the l2 test, divided by the walk kernel's
+                measured duration (HIP events on its launch stream);
+  ttfs          time to the first verified solution per instance (plain
+                order, mode first), when --ttfs is given;
+  cpu_baseline  the CPU oracle (plain recursive C enumerator, all host cores)
+                on a time-capped sample of the first instance.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
+
+WORKLOADS = {
+    # name: (description, list of (m, D, seed))
+    "m9": ("12 planted instances m=9, n=80, 4 each D=50/100/200 (seeds 4500-4511), exhaustive",
+           [(9, (50, 100, 200)[i // 4], 4500 + i) for i in range(12)]),
+    "m9-d200": ("4 planted instances m=9, n=80, D=200 (seeds 4508-4511), exhaustive",
+                [(9, 200, 4508 + i) for i in range(4)]),
+    "m9-1": ("1 planted instance m=9, n=80, D=200 (seed 4508), exhaustive",
+             [(9, 200, 4508)]),
+    "m8": ("4 planted instances m=8, n=70, D=100 (seeds 4000-4003), exhaustive",
+           [(8, 100, 4000 + i) for i in range(4)]),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="m9-1", choices=sorted(WORKLOADS))
+    ap.add_argument("--ttfs", action="store_true", help="also time first-solution search per instance")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--time-cap-ms", type=float, default=600000.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import msp_instances as mi
+    import paper_2508_08702_amd as M
+
+    desc, spec = WORKLOADS[args.workload]
+    insts = [mi.msp_class(m, D, s) for (m, D, s) in spec]
+    dev = torch.device("cuda", 0)
+    dev_in = [(torch.from_numpy(i.A).to(dev), torch.from_numpy(i.d).to(dev)) for i in insts]
+    ctx = M.Context(0)
+    prm = M.msp_params_default(time_cap_ms=args.time_cap_ms)
+    out = torch.zeros((1 << 16, max(i.n for i in insts)), dtype=torch.uint8, device=dev)
+
+    def step(record):
+        tot_nodes = tot_evals = 0
+        for inst, (A, d) in zip(insts, dev_in):
+            Bk = M.msp_reduce(ctx, A, d, prm)
+            o = out[:, : inst.n].contiguous()
+            r = M.msp_enumerate(ctx, A, d, Bk, params=prm, out=o, cap=o.shape[0])
+            if r.status != M.MSP_OK:
+                raise RuntimeError(f"enumeration status {r.status} ({M.msp_strerror(r.status)})")
+            xs = r.x.cpu().numpy().astype(np.int64)
+            if xs.shape[0] == 0 or not np.all(xs @ inst.A.T.astype(np.int64) == inst.d[None, :]):
+                raise RuntimeError("a returned row does not satisfy A x = d")
+            st = r.stats
+            tot_nodes += st["nodes"]
+            tot_evals += st["evals"]
+            if record is not None:
+                record.append((inst, st))
+        return tot_nodes, tot_evals
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    nodes = 0
+    for _ in range(args.steps):
+        n_, _e = step(rec)
+        nodes += n_
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # roofline of the walk kernel: algorithmic flops over measured kernel time
+    flops = 0.0
+    kern_s = 0.0
+    for inst, st in rec:
+        dim = inst.n + 1
+        flops += st["nodes"] * (3 * dim + 4) + (st["evals"] - st["nodes"]) * 4
+        kern_s += st["kernel_ms"] * 1e-3
+    achieved = flops / kern_s / 1e12 if kern_s > 0 else 0.0
+    res = {
+        "metric": "enum nodes/s + time-to-first-solution, m=9..11, plain vs learned order",
+        "value": nodes / wall,
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances": len(insts), "mode": "all", "order": "plain",
+                   "nodes_per_step": nodes // max(1, args.steps)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "walk_kernel", "walk_ms_total": kern_s * 1e3,
+                     "walk_launches": len(rec), "walk_ms_avg": kern_s * 1e3 / max(1, len(rec)),
+                     "flops_per_node": "3*(n+1)+4, plus 4 per failed candidate"},
+        "phase_ms_per_step": {
+            k: sum(st[k] for _, st in rec) / args.steps
+            for k in ("gs_ms", "rootgen_ms", "kernel_ms", "total_ms")
+        },
+    }
+    if args.ttfs:
+        tt = []
+        fprm = M.msp_params_default(time_cap_ms=args.time_cap_ms)
+        for inst, (A, d) in zip(insts, dev_in):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Bk = M.msp_reduce(ctx, A, d, fprm)
+            r = M.msp_enumerate(ctx, A, d, Bk, params=fprm, mode=M.MSP_FIRST, cap=64)
+            torch.cuda.synchronize()
+            e2e = (time.perf_counter() - t1) * 1e3
+            xs = r.x.cpu().numpy().astype(np.int64)
+            ok = xs.shape[0] > 0 and bool(np.all(xs @ inst.A.T.astype(np.int64) == inst.d[None, :]))
+            tt.append({"seed": inst.seed, "D": inst.D, "ttfs_kernel_ms": r.stats["ttfs_ms"],
+                       "end_to_end_ms": e2e, "verified": ok})
+        res["ttfs"] = {"order": "plain", "median_end_to_end_ms": statistics.median(t["end_to_end_ms"] for t in tt),
+                       "per_instance": tt}
+    if not args.no_cpu_baseline:
+        from oracle import enum as E
+        from oracle import lattice as L
+        inst = insts[0]
+        P = L.prepare(inst.A, inst.d)
+        cores = os.cpu_count() or 1
+        r = E.enumerate_prepared(P, split=12, threads=cores, time_cap_s=args.cpu_seconds)
+        res["cpu_baseline"] = {"value": r.nodes / r.seconds, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+                               "sample": f"instance m={inst.m} D={inst.D} seed={inst.seed}, first "
+                                         f"{r.seconds:.1f} s of the exhaustive enumeration (time cap), "
+                                         f"{r.nodes} nodes"}
+    ctx.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,8 @@ struct msp_ctx {
     Buf stack;
     Buf ctl;
     Buf order;
+    Buf lll_desc, lll_work;
+    long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
 };
 
@@ -210,6 +212,8 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->stack.release();
     c->ctl.release();
     c->order.release();
+    c->lll_desc.release();
+    c->lll_work.release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;
@@ -395,10 +399,58 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     return MSP_OK;
 }
 
-int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *p,
+int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *pin,
                int64_t *basis_dev, int *k_out, void *stream) {
-    (void)c; (void)m; (void)n; (void)A_dev; (void)d_dev; (void)p; (void)basis_dev; (void)k_out; (void)stream;
-    return MSP_E_UNSUPPORTED;
+    if (!c || !A_dev || !d_dev || !basis_dev || !k_out) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    *k_out = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = n + 1, len = m + n + 1;
+    // one-instance descriptor block: m, n | A_off, d_off, work_off, out_off | status, kout | iters
+    struct Desc {
+        int m, n;
+        int64_t A_off, d_off, work_off, out_off;
+        int32_t status, kout;
+        long long iters;
+    };
+    MSP_TRY(c->lll_desc.ensure(sizeof(Desc)));
+    MSP_TRY(c->lll_work.ensure((size_t)nv * len * sizeof(long long)));
+    Desc h{m, n, 0, 0, 0, 0, 0, 0, 0};
+    Desc *dd = c->lll_desc.as<Desc>();
+    MSP_TRY(hipMemcpyAsync(dd, &h, sizeof(Desc), hipMemcpyHostToDevice, st));
+    LllArgs la{};
+    la.m = &dd->m;
+    la.n = &dd->n;
+    la.A = A_dev;
+    la.A_off = &dd->A_off;
+    la.d = d_dev;
+    la.d_off = &dd->d_off;
+    la.N = p.N;
+    la.delta = p.delta;
+    la.max_iters = 2000000;
+    la.work = c->lll_work.as<long long>();
+    la.work_off = &dd->work_off;
+    la.out = basis_dev;
+    la.out_off = &dd->out_off;
+    la.status = &dd->status;
+    la.kout = &dd->kout;
+    la.iters = &dd->iters;
+    MSP_TRY(launch_lll(la, 1, n, st));
+    MSP_TRY(hipMemcpyAsync(&h, dd, sizeof(Desc), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    c->last_lll_iters = h.iters;
+    switch (h.status) {
+        case 0: *k_out = h.kout; return MSP_OK;
+        case -2: return MSP_E_RANK;
+        case -3: return MSP_E_NOT_ISOLATED;
+        case -4: return MSP_E_OVERFLOW;
+        default: return MSP_E_NUMERIC;
+    }
 }
 
 }  // extern "C"

@@ -91,4 +91,24 @@ struct WalkArgs {
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);
 size_t walk_lds_bytes(int dimp, int block, int k, int L);
 
+struct LllArgs {
+    const int *m, *n;              // per instance
+    const int32_t *A;              // packed instances; A of instance i at A + A_off[i] (m x n)
+    const int64_t *A_off;
+    const int64_t *d;              // d of instance i at d + d_off[i]
+    const int64_t *d_off;
+    long long N;                   // scale constant of eq. (2)
+    double delta;                  // Lovász parameter
+    long long max_iters;           // LLL iteration cap
+    long long *work;               // basis workspace, instance i at work + work_off[i] ((n+1) x (m+n+1))
+    const int64_t *work_off;
+    int64_t *out;                  // kernel basis of instance i at out + out_off[i] (k x (n+1))
+    const int64_t *out_off;
+    int32_t *status;               // 0, -2 (rank), -3 (not isolated), -4 (overflow), -10 (no convergence)
+    int32_t *kout;                 // zero-top vectors found
+    long long *iters;              // LLL iterations used
+};
+hipError_t launch_lll(const LllArgs &a, int ninst, int max_n, hipStream_t st);
+size_t lll_lds_bytes(int n);
+
 }  // namespace msp
