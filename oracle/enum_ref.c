@@ -11,7 +11,8 @@
  * projected vector w' by value (its own copy), as in Algorithm 1.
  *
  * The level-t step (Section 2, "First/Second pruning condition", Alg. 1):
- *   y_t  = sum_{i>t} u_i mu_{i,t}          centre of level t is c = -y_t
+ *   y_t  = sum_{i>t} u_i mu_{i,t}          centre of level t is c = -y_t,
+ *                                          summed from i = k-1 down to t+1
  *   x    = u_t + y_t
  *   l    = x^2 beta_t + l'                 ||w^(t)||^2 by the recurrence
  *   prune (return) when l > R (1 + eps)    R = (n+1) r_max^2
@@ -29,6 +30,8 @@
  *   - the sign symmetry v <-> -v is broken: while every u_i above t is 0,
  *     only u_t = 0, 1, 2, ... is tried, and the first Hoelder failure there
  *     ends the level (its mirror image fails as well);
+ *   - the centre sum runs from the top level down, the order in which the
+ *     search fixes the u_i;
  *   - eps = 1e-9 relative slack on both tests (solutions lie exactly on the
  *     l2 bound);
  *   - the r_max coordinate is the last one (index n): a solution has
@@ -194,7 +197,7 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
     const int k = a->k, dim = a->dim;
     double w[ORC_MAXDIM];
     double y = 0.0;
-    for (int i = t + 1; i < k; ++i) y += (double)W->u[i] * a->mu[(int64_t)i * k + t];
+    for (int i = k - 1; i > t; --i) y += (double)W->u[i] * a->mu[(int64_t)i * k + t];
     const double c = -y;
     const double bound = a->R * (1.0 + a->eps);
     int u1, s, off = 0, onedir, dir;
