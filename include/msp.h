@@ -70,7 +70,7 @@ typedef struct {
     double delta;         /* LLL Lovász parameter                            [0.99] */
     double eps;           /* relative slack of both pruning tests            [1e-9] */
     int split_depth;      /* levels enumerated before the subtree split; -1 = auto [-1] */
-    int block;            /* threads per workgroup of the walk kernel; 0 = auto  [0] */
+    int block;            /* walk kernel workgroup size cap (256|512); 0 = auto [0] */
     int target_roots;     /* root count the automatic split aims for; 0 = auto  [0] */
     int hoelder;          /* 1: apply the Hoelder test (Thm 2)                  [1] */
     int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
@@ -83,9 +83,12 @@ typedef struct {
  * was descended into; leaf = a node at level 0. */
 typedef struct {
     int64_t evals, nodes, expansions, leaves;
-    int64_t roots;           /* subtree roots in the queue                       */
+    int64_t roots;           /* subtree roots from root generation               */
+    int64_t items;           /* work items walked (roots plus split-off items)   */
     int32_t split_depth;     /* split depth used                                 */
     int32_t k;               /* kernel lattice rank n - m + 1                    */
+    int32_t block;           /* threads per workgroup of the walk kernel         */
+    int32_t pad;
     double reduce_ms;        /* msp_reduce (embedding + LLL + extraction)        */
     double gs_ms;            /* Gram-Schmidt kernel                              */
     double rootgen_ms;       /* root generation (levels above the split)         */

@@ -59,7 +59,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [
         ("evals", C.c_int64), ("nodes", C.c_int64), ("expansions", C.c_int64), ("leaves", C.c_int64),
-        ("roots", C.c_int64), ("split_depth", C.c_int32), ("k", C.c_int32),
+        ("roots", C.c_int64), ("items", C.c_int64), ("split_depth", C.c_int32), ("k", C.c_int32),
+        ("block", C.c_int32), ("pad", C.c_int32),
         ("reduce_ms", C.c_double), ("gs_ms", C.c_double), ("rootgen_ms", C.c_double),
         ("ordering_ms", C.c_double), ("kernel_ms", C.c_double), ("ttfs_ms", C.c_double),
         ("total_ms", C.c_double),

@@ -74,7 +74,9 @@ struct FrontierBuf {
 // Small device-side control block, one allocation.
 struct Ctl {
     unsigned long long counters[8];  // evals nodes expansions leaves roots
-    unsigned long long qhead;
+    unsigned long long qhead;      // pool claim cursor
+    unsigned long long qtail;      // pool append cursor
+    long long pending;             // unfinished pool items
     unsigned long long n_found;
     unsigned long long t_first;
     unsigned long long t_start;
@@ -97,6 +99,8 @@ struct msp_ctx {
     Buf ctl;
     Buf order;
     Buf lll_desc, lll_work;
+    Buf g_bh, g_muc, g_coff;
+    Buf pool_u, pool_meta, pool_ready;
     long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
 };
@@ -214,6 +218,12 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->order.release();
     c->lll_desc.release();
     c->lll_work.release();
+    c->g_bh.release();
+    c->g_muc.release();
+    c->g_coff.release();
+    c->pool_u.release();
+    c->pool_meta.release();
+    c->pool_ready.release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;
@@ -254,8 +264,7 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     const int dimp = dimp_for(dim);
     if (dimp < 0) return MSP_E_UNSUPPORTED;
     const int ws = dimp + kWsTail;
-    const int block = 256;
-    if (p.block != 0 && p.block != block) return MSP_E_UNSUPPORTED;
+    if (p.block != 0 && p.block != 256 && p.block != 512) return MSP_E_ARG;
 
     // ---- Gram-Schmidt (step 3) ----
     MSP_TRY(c->gs_bhat.ensure((size_t)k * dim * sizeof(double)));
@@ -278,9 +287,8 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     const double hfac = 1.0 + p.eps;
 
     // ---- root generation: levels k-1 .. L breadth first ----
-    const int per_cu_max = 2;
-    const int64_t walkers = (int64_t)c->num_cus * per_cu_max * block;
-    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(8 * walkers, 4096);
+    const int64_t walkers = (int64_t)c->num_cus * 512;  // largest grid of the walk kernel
+    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(4 * walkers, 4096);
     const int64_t fcap = std::max<int64_t>(4 * target, 1 << 16);
     MSP_TRY(c->fr[0].ensure(fcap, k, ws));
     MSP_TRY(c->fr[1].ensure(fcap, k, ws));
@@ -330,26 +338,49 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     MSP_TRY(hipEventRecord(c->ev[3], st));
 
     // ---- subtree walk (levels L-1 .. 0) ----
-    const size_t lds = walk_lds_bytes(dimp, block, k, L);
-    if (lds > 160 * 1024) return MSP_E_UNSUPPORTED;
-    MSP_TRY(c->stack.ensure((size_t)walkers * k * 4 * sizeof(double)));
+    int wblock = walk_block_for(dimp, k, L);
+    if (p.block != 0 && wblock != 0) wblock = std::min(wblock, p.block);
+    if (wblock == 0) return MSP_E_UNSUPPORTED;
+    const int muc_len = walk_muc_len(k);
+    const int S = walk_row_stride(dimp);
+    MSP_TRY(c->g_bh.ensure((size_t)k * S * sizeof(double)));
+    MSP_TRY(c->g_muc.ensure((size_t)muc_len * sizeof(double)));
+    MSP_TRY(c->g_coff.ensure((size_t)(k + 2) * sizeof(int)));
+    MSP_TRY(launch_walk_prep(k, dim, dimp, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->g_bh.as<double>(),
+                             c->g_muc.as<double>(), c->g_coff.as<int>(), st));
+    const int64_t nwalk = (int64_t)c->num_cus * wblock;
+    MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));
+    const int64_t pcap = np + std::max<int64_t>(256 * nwalk, 1 << 22);
+    MSP_TRY(c->pool_u.ensure((size_t)pcap * k));
+    MSP_TRY(c->pool_meta.ensure((size_t)pcap * sizeof(int4)));
+    MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));
+    Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), pcap};
     if (np > 0) {
+        MSP_TRY(launch_pool_init(c->fr[cur].view(), np, k, L, pool, st));
+        const unsigned long long qt = (unsigned long long)np;
+        const long long pend = (long long)np;
+        MSP_TRY(hipMemcpyAsync(&ctl->qtail, &qt, sizeof(qt), hipMemcpyHostToDevice, st));
+        MSP_TRY(hipMemcpyAsync(&ctl->pending, &pend, sizeof(pend), hipMemcpyHostToDevice, st));
         WalkArgs wa{};
         wa.k = k;
         wa.dim = dim;
         wa.n = n;
         wa.m = m;
         wa.L = L;
-        wa.bhat = c->gs_bhat.as<double>();
-        wa.mu = c->gs_mu.as<double>();
+        wa.g_bh = c->g_bh.as<double>();
+        wa.g_muc = c->g_muc.as<double>();
+        wa.g_coff = c->g_coff.as<int>();
+        wa.muc_len = muc_len;
         wa.beta = c->gs_beta.as<double>();
         wa.basis = basis_dev;
         wa.A = A_dev;
         wa.d = d_dev;
-        wa.roots = c->fr[cur].view();
+        wa.pool = pool;
         wa.nroots = np;
         wa.order = nullptr;
-        wa.qhead = &ctl->qhead;
+        wa.head = &ctl->qhead;
+        wa.tail = &ctl->qtail;
+        wa.pending = &ctl->pending;
         wa.stack = c->stack.as<double>();
         wa.x_out = x_dev;
         wa.cap = cap;
@@ -365,7 +396,7 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
         wa.hoelder = p.hoelder;
         wa.onedir = p.onedir;
         MSP_TRY(hipEventRecord(c->ev[4], st));
-        MSP_TRY(launch_walk(wa, dimp, block, c->num_cus, st));
+        MSP_TRY(launch_walk(wa, dimp, wblock, c->num_cus, st));
         MSP_TRY(hipEventRecord(c->ev[5], st));
     } else {
         MSP_TRY(hipEventRecord(c->ev[4], st));
@@ -383,6 +414,8 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
         stats->expansions = (int64_t)h.counters[2];
         stats->leaves = (int64_t)h.counters[3];
         stats->roots = np;
+        stats->items = (int64_t)h.counters[4];
+        stats->block = wblock;
         stats->split_depth = k - L;
         stats->k = k;
         stats->gs_ms = elapsed(c->ev[0], c->ev[1]);

@@ -64,21 +64,40 @@ hipError_t launch_frontier_init(Frontier f, int k, int ws, hipStream_t st);
 // exclusive prefix sum of counts[0..n) into offs, total into *total
 hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t *total, hipStream_t st);
 
+// Work-item pool of the walker: item i = (level T, prefix u_{T+1..k-1},
+// zig-zag continuation at level T).
+//   u     int8 [cap x k]  prefix (natural level index; entries <= T are 0)
+//   meta  int4 [cap]      {T, u_start, flags (onedir 1, dir>0 2, topzero 4,
+//                          fresh 8: start the level from its first value), 0}
+//   ready int  [cap]      set (release) once a donated item is fully written
+struct Pool {
+    int8_t *u;
+    int4 *meta;
+    int *ready;
+    int64_t cap;
+};
+
 struct WalkArgs {
-    int k, dim, n, m, L;           // L: level of the roots; walkers live on levels < L
-    const double *bhat, *mu, *beta;
+    int k, dim, n, m, L;           // L: split level; walkers live on levels < L
+    const double *g_bh;            // k x S rotated rows (see walk.hip)
+    const double *g_muc;           // mu by columns, column t at g_coff[t]
+    const int *g_coff;             // k + 1 column offsets
+    int muc_len;                   // doubles in g_muc
+    const double *beta;            // k
     const int64_t *basis;          // k x dim, exact leaf reconstruction
     const int32_t *A;
     const int64_t *d;
-    Frontier roots;
-    int64_t nroots;
-    const int64_t *order;          // optional permutation of roots (nullptr = identity)
-    unsigned long long *qhead;     // next root index
+    Pool pool;
+    int64_t nroots;                // items 0..nroots-1 come from root generation
+    const int64_t *order;          // optional permutation of those (nullptr = identity)
+    unsigned long long *head;      // next ticket
+    unsigned long long *tail;      // next free pool slot
+    long long *pending;            // items created and not yet finished
     double *stack;                 // per walker k entries x 4 doubles
     uint8_t *x_out;
     int64_t cap;
     unsigned long long *n_found;
-    unsigned long long *counters;  // [0] evals [1] nodes [2] expansions [3] leaves [4] roots done
+    unsigned long long *counters;  // [0] evals [1] nodes [2] expansions [3] leaves [4] items done
     int *flags;                    // [0] stop [1] overflow [2] timeout [3] internal error
     unsigned long long *t_first;   // wall clock of the first verified hit (0 = none)
     unsigned long long *t_start;   // wall clock when the kernel started
@@ -87,9 +106,14 @@ struct WalkArgs {
     double bound, hfac;
     int hoelder, onedir;
 };
-// Returns hipErrorInvalidValue when no compiled variant fits (dim, k, L).
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);
-size_t walk_lds_bytes(int dimp, int block, int k, int L);
+hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
+                            double *g_muc, int *g_coff, hipStream_t st);
+size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len);
+__host__ __device__ int walk_row_stride(int dimp);
+int walk_muc_len(int k);
+int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
+hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
 
 struct LllArgs {
     const int *m, *n;              // per instance

@@ -125,6 +125,18 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int64_t *counts, int64
     if (threadIdx.x == 1023) *total = part[1023];
 }
 
+// Root generation's last frontier becomes the first pool items: level L-1,
+// prefix u_{L..k-1}, starting at the level's first value.
+__global__ void pool_init_kernel(Frontier f, int64_t nroots, int k, int L, Pool pool) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nroots) {
+        for (int j = 0; j < k; ++j) pool.u[i * k + j] = j >= L ? f.u[i * k + j] : (int8_t)0;
+        pool.meta[i] = make_int4(L - 1, 0, 8 | (f.tz[i] ? 4 : 0), 0);
+        pool.ready[i] = 1;
+    }
+    for (int64_t j = nroots + i; j < pool.cap; j += (int64_t)gridDim.x * blockDim.x) pool.ready[j] = 0;
+}
+
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st) {
@@ -141,6 +153,12 @@ hipError_t launch_expand_write(const ExpandArgs &a, hipStream_t st) {
 
 hipError_t launch_frontier_init(Frontier f, int k, int ws, hipStream_t st) {
     hipLaunchKernelGGL(frontier_init_kernel, dim3(1), dim3(256), 0, st, f, k, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st) {
+    const int64_t n = nroots > (1 << 18) ? nroots : (1 << 18);
+    hipLaunchKernelGGL(pool_init_kernel, dim3(grid_for(n)), dim3(256), 0, st, f, nroots, k, L, pool);
     return hipGetLastError();
 }
 

@@ -1,36 +1,41 @@
 // Persistent subtree walker: Algorithm 1 (paper, Section 2) below the split
-// level, one subtree per lane.
+// level, one work item per lane.
 //
-// Work distribution.  The grid is one or two workgroups per CU and stays
-// resident; each lane that needs work takes the next subtree root from the
-// queue (wave ballot + one atomic per wave + prefix count), walks that
-// subtree to the end, and takes the next.  Walkers run until the queue is
-// empty or, in first-solution mode, until a verified hit raises the stop flag.
+// Work items.  An item is (level T, prefix u_{T+1..k-1}, zig-zag
+// continuation at level T): "enumerate the remaining values of u_T after the
+// given prefix, and everything below them".  Root generation supplies the
+// first items (T = split level - 1, continuation = the level's first value).
+// Items sit in an HBM pool.  A lane without work takes a ticket (one atomic
+// add on the head counter per wave, ranks by ballot prefix count); ticket i
+// is pool slot i, and the lane waits until that slot holds an item.  While
+// head > tail -- lanes are waiting -- every busy lane donates the untried
+// values of its highest open level as a new item appended at the tail (tree
+// partitioning, paper Section 4), so the work is split dynamically and no
+// lane is left with a huge subtree at the end.  A count of unfinished items
+// (pending) ends the walk: a waiting lane stops once it reaches zero.  A lane that takes an item
+// recomputes centres, partial norms and w for the prefix, top level first, in
+// the same order as the oracle; evaluations are never duplicated, so the
+// search-tree counters are exactly those of a sequential run.
 //
-// Per-lane state.  The projected vector w (Section 2: w^(t) = x_t b_hat_t +
-// w^(t+1)) lives in DIMP registers.  It is updated incrementally: a new
-// candidate at level t adds (u - u_applied) b_hat_t (an integer multiple) or
-// x b_hat_t on first use of the level, and leaving level t subtracts the
-// applied x_t b_hat_t.  Each loop iteration performs exactly one such row
-// update per lane -- a node's update or a level's revert -- so all lanes run
-// the expensive dim-length pass in lockstep; the cheap scalar control around
-// it may diverge.
+// Per-lane state.  w (Section 2: w^(t) = x_t b_hat_t + w^(t+1)) lives in DIMP
+// registers and is updated incrementally: a new candidate at level t adds
+// (u - u_applied) b_hat_t, or x b_hat_t on first use of the level, and
+// leaving level t subtracts the applied x_t b_hat_t.  Each loop iteration
+// performs exactly one such row update per lane, so all lanes run the
+// expensive pass in lockstep; the cheap scalar control around it diverges.
+// The state of the level above (centre, partial norm, beta, u, flags) is kept
+// in registers, so popping a level waits for no memory; the level above that
+// is fetched from the per-walker HBM stack while the walk goes on.
 //
-// LDS.  Rows b_hat_0..b_hat_{L-1} are stored with a padded stride S (a
-// multiple of 16 doubles) and a wrap-around copy of their first 14 columns.
-// Lane l keeps w in the column order rotated by r = 2 (l mod 8): register j
-// holds column (j + r) mod DIMP and the pass reads row[r + j].  Eight lanes
-// that read eight arbitrary rows then hit eight distinct 16-byte bank groups,
-// so the 128-bit LDS reads are free of bank conflicts no matter which levels
-// the lanes are on.  Only l1 norms and elementwise updates touch w, and both
-// are independent of the column order.
-// The strictly lower triangle of mu, beta, and an int8 stack of u values
-// ([level][thread], for the centre sums and the leaf check) complete the LDS.
-//
-// Per-walker stack (HBM, one 32-byte entry per level: centre y, parent
-// partial norm, zig-zag flags).  The state of the level above the current one
-// is cached in registers, so popping a level never waits for memory; the
-// entry above that is fetched while the walk continues.
+// LDS.  Rows b_hat_0..b_hat_{L-1} with a padded stride S (a multiple of 16
+// doubles) and a wrap-around copy of the first 14 columns.  Lane l keeps w in
+// the column order rotated by r = 2 (l mod 8): register j holds column
+// (j + r) mod DIMP and the pass reads row[r + j], so eight lanes reading
+// eight arbitrary rows hit eight distinct 16-byte bank groups.  Only l1
+// norms and elementwise updates touch w; both ignore the column order.
+// mu is stored by columns (column t = mu_{k-1,t}, mu_{k-2,t}, ..., mu_{t+1,t},
+// zero padded to a multiple of 8) and each thread keeps its u values in a
+// reversed int8 row, so a centre sum reads 8 levels per chunk.
 #include "enum_rules.h"
 #include "msp_internal.h"
 
@@ -38,66 +43,122 @@ namespace msp {
 
 namespace {
 
-enum : int { NEED_ROOT = 0, RUN = 1, DONE = 2 };
+enum : int { NEED_ROOT = 0, RUN = 1, DONE = 2, WAIT = 3 };
 enum : int { K_NONE = 0, K_NODE = 1, K_REVERT = 2 };
+enum : int { F_ONEDIR = 1, F_DIRPOS = 2, F_TZ = 4, F_FRESH = 8 };
 
 constexpr int kRot = 2;  // rotation granule (columns): 128-bit reads
 
-template <int DIMP>
-struct Lds {
-    static constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
-};
-
 __device__ __forceinline__ unsigned long long wall_clock() { return wall_clock64(); }
 
-__device__ __forceinline__ int load_flag(int *p) {
+__device__ __forceinline__ int ld_acq(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_rlx(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long ld_rlx(const long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// centre sum of level t, top level first (8 levels per chunk).  my_u[p] holds
+// u_{k-1-p}; col[p] = mu_{k-1-p,t}, zero beyond the column's k-1-t entries.
+__device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, const double *col) {
+    const int nt = k - 1 - t;
+    double y = 0.0;
+    for (int c = 0; c < nt; c += 8) {
+        const uint2 uu = *reinterpret_cast<const uint2 *>(my_u + c);
+        const double2 m0 = *reinterpret_cast<const double2 *>(col + c);
+        const double2 m1 = *reinterpret_cast<const double2 *>(col + c + 2);
+        const double2 m2 = *reinterpret_cast<const double2 *>(col + c + 4);
+        const double2 m3 = *reinterpret_cast<const double2 *>(col + c + 6);
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.x), m0.x));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 8), m0.y));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 16), m1.x));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 24), m1.y));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.y), m2.x));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 8), m2.y));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 16), m3.x));
+        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 24), m3.y));
+    }
+    return y;
 }
 
 }  // namespace
 
+__host__ __device__ int walk_row_stride(int dimp) { return ((dimp + kRotMax + 15) / 16) * 16; }
+__host__ __device__ int walk_u_stride(int k) { return ((k + 7) / 8) * 8; }
+
+size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len) {
+    const int S = walk_row_stride(dimp);
+    return sizeof(double) * ((size_t)L * S + (size_t)muc_len + (size_t)k) + sizeof(int) * (size_t)((k + 2) & ~1) +
+           (size_t)walk_u_stride(k) * block;
+}
+
+// Layouts used by the walker: rotated rows (k x S) and mu by columns.
+__global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
+                                 double *g_muc, int *g_coff) {
+    const int S = walk_row_stride(dimp);
+    const int t = blockIdx.x;
+    if (t < k) {
+        for (int p = threadIdx.x; p < S; p += blockDim.x) {
+            double v = 0.0;
+            if (p < dimp + kRotMax) {
+                const int c = p < dimp ? p : p - dimp;
+                if (c < dim) v = bhat[(size_t)t * dim + c];
+            }
+            g_bh[(size_t)t * S + p] = v;
+        }
+        int off = 0;
+        for (int tt = 0; tt < t; ++tt) off += ((k - 1 - tt + 7) / 8) * 8;
+        const int nt = k - 1 - t, np = ((nt + 7) / 8) * 8;
+        for (int p = threadIdx.x; p < np; p += blockDim.x)
+            g_muc[off + p] = p < nt ? mu[(size_t)(k - 1 - p) * k + t] : 0.0;
+        if (threadIdx.x == 0) {
+            g_coff[t] = off;
+            if (t == k - 1) g_coff[k] = off + np;
+        }
+    }
+}
+
 template <int DIMP, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
-    constexpr int S = Lds<DIMP>::S;
+    constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k, L = a.L, tid = threadIdx.x;
-    double *s_bh = reinterpret_cast<double *>(smem);          // L x S
-    double *s_mu = s_bh + (size_t)L * S;                      // row i (1..k-1) at i(i-1)/2
-    double *s_beta = s_mu + (size_t)k * (k - 1) / 2;          // L (padded to even)
-    int8_t *s_u = reinterpret_cast<int8_t *>(s_beta + ((L + 1) & ~1));  // k x BLOCK
+    const int KU = ((k + 7) / 8) * 8;
+    double *s_bh = reinterpret_cast<double *>(smem);  // L x S
+    double *s_muc = s_bh + (size_t)L * S;             // mu columns
+    double *s_beta = s_muc + a.muc_len;               // k
+    int *s_coff = reinterpret_cast<int *>(s_beta + k);  // k + 1 (padded to even)
+    int8_t *s_u = reinterpret_cast<int8_t *>(s_coff + ((k + 2) & ~1));  // BLOCK x KU
 
-    for (int idx = tid; idx < L * S; idx += BLOCK) {
-        const int t = idx / S, p = idx - t * S;
-        double v = 0.0;
-        if (p < DIMP + kRotMax) {
-            const int c = p < DIMP ? p : p - DIMP;
-            if (c < a.dim) v = a.bhat[(size_t)t * a.dim + c];
-        }
-        s_bh[idx] = v;
-    }
-    for (int i = 1; i < k; ++i)
-        for (int j = tid; j < i; j += BLOCK) s_mu[i * (i - 1) / 2 + j] = a.mu[(size_t)i * k + j];
-    for (int t = tid; t < L; t += BLOCK) s_beta[t] = a.beta[t];
-    for (int idx = tid; idx < k * BLOCK; idx += BLOCK) s_u[idx] = 0;
+    for (int idx = tid; idx < L * S; idx += BLOCK) s_bh[idx] = a.g_bh[idx];
+    for (int idx = tid; idx < a.muc_len; idx += BLOCK) s_muc[idx] = a.g_muc[idx];
+    for (int t = tid; t < k; t += BLOCK) s_beta[t] = a.beta[t];
+    for (int t = tid; t <= k; t += BLOCK) s_coff[t] = a.g_coff[t];
+    for (int idx = tid; idx < KU * BLOCK; idx += BLOCK) s_u[idx] = 0;
     __syncthreads();
 
     const int lane = tid & 63;
     const int rot = kRot * (lane & 7);
     const int64_t walker = (int64_t)blockIdx.x * BLOCK + tid;
     double *stk = a.stack + walker * (int64_t)k * 4;
-    const int ws = DIMP + kWsTail;
+    int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
     double w[DIMP];
 #pragma unroll
     for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
 
     int state = NEED_ROOT, fex = 0;
-    int t = 0, u = 0, onedir = 0, dir = 1, tz = 0, applied = 0, u_app = 0;
+    long long ticket = 0;
+    int t = 0, u = 0, onedir = 0, dir = 1, tz = 0, applied = 0, u_app = 0, top = 0;
     Zig z{0, 1};
-    double y = 0.0, lpar = 0.0, lcur = 0.0;
-    double Py = 0.0, Pl = 0.0;  // cached state of level t+1
-    int Pf = 0;
-    unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_roots = 0;
+    double y = 0.0, lpar = 0.0, lcur = 0.0, bt = 1.0;
+    double Py = 0.0, Pl = 0.0, Pbt = 1.0;  // cached state of level t+1
+    int Pu = 0, Pf = 0;
+    unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;
     unsigned iter = 0;
     unsigned long long t_end = 0;
     if (lane == 0) {
@@ -106,12 +167,8 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         t_end = a.deadline ? t0 + a.deadline : 0;
     }
 
-    // centre of level t from the u stack (levels > t), then the zig-zag start
-    auto enter_level = [&]() {
-        double yy = 0.0;
-        for (int i = k - 1; i > t; --i)
-            yy = add_rn(yy, mul_rn((double)s_u[i * BLOCK + tid], s_mu[i * (i - 1) / 2 + t]));
-        y = yy;
+    auto enter_level = [&]() {  // level t freshly entered from above
+        y = centre_sum(t, k, my_u, s_muc + s_coff[t]);
         z = zig_init(y, tz != 0);
         onedir = tz;
         dir = 1;
@@ -121,56 +178,146 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     auto advance = [&]() { u = onedir ? u + dir : zig_next(z, u); };
 
     for (;;) {
-        if ((iter++ & 63u) == 0) {
+        const unsigned phase = iter++ & 31u;
+        if (phase == 0) {
             int stop = 0;
             if (lane == 0) {
-                stop = load_flag(&a.flags[0]);
+                stop = ld_acq(&a.flags[0]);
                 if (!stop && t_end && wall_clock() > t_end) {
                     atomicOr(&a.flags[2], 1);
                     atomicOr(&a.flags[0], 1);
                     stop = 1;
                 }
             }
-            stop = __shfl(stop, 0, 64);
-            if (stop) state = DONE;
+            if (__shfl(stop, 0, 64)) state = DONE;
+        } else if (phase == 16) {
+            // ---- donation: split off the untried values of the highest open level,
+            // while lanes hold tickets beyond the last item (head > tail) ----
+            int want = 0;
+            if (lane == 0) {
+                const unsigned long long h = ld_rlx(a.head), tl = ld_rlx(a.tail);
+                want = h > tl;
+            }
+            if (__shfl(want, 0, 64)) {
+                bool cand = state == RUN && top > t;
+                int D = top, un = 0, fD = 0;
+                if (cand) {
+                    double yD, lD, bD;
+                    int uD;
+                    if (D == t + 1) {
+                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf;
+                    } else {
+                        const double *e = stk + (size_t)D * 4;
+                        yD = e[0]; lD = e[1]; fD = (int)e[2];
+                        bD = s_beta[D];
+                        uD = my_u[k - 1 - D];
+                    }
+                    const int odD = fD & F_ONEDIR, drD = (fD & F_DIRPOS) ? 1 : -1;
+                    const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
+                    un = odD ? uD + drD : zig_next(zD, uD);
+                    const double l = partial_norm(add_rn((double)un, yD), bD, lD);
+                    if (!(l <= a.bound)) {
+                        // nothing untried left at level D: this is the failing
+                        // evaluation that would end level D, so count it here
+                        ++c_eval;
+                        top = D - 1;
+                        cand = false;
+                    }
+                }
+                const unsigned long long dm = __ballot(cand);
+                if (dm) {
+                    const int cnt = __popcll(dm);
+                    const int leader = __ffsll((long long)dm) - 1;
+                    int valid = 0;
+                    unsigned long long base = 0;
+                    if (lane == leader) {
+                        base = atomicAdd(a.tail, (unsigned long long)cnt);
+                        const long long room = (long long)a.pool.cap - (long long)base;
+                        valid = room <= 0 ? 0 : (room < cnt ? (int)room : cnt);
+                        if (valid) atomicAdd((unsigned long long *)a.pending, (unsigned long long)valid);
+                    }
+                    base = __shfl(base, leader, 64);
+                    valid = __shfl(valid, leader, 64);
+                    const int rank = __popcll(dm & lt_mask);
+                    if (cand && rank < valid) {
+                        const int64_t slot = (int64_t)base + rank;
+                        int8_t *pu = a.pool.u + slot * k;
+                        for (int j = 0; j < k; ++j) pu[j] = j > D ? my_u[k - 1 - j] : (int8_t)0;
+                        a.pool.meta[slot] = make_int4(D, un, fD & (F_ONEDIR | F_DIRPOS | F_TZ), 0);
+                        __hip_atomic_store(&a.pool.ready[slot], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        top = D - 1;
+                    }
+                }
+            }
         }
-        // ---- take roots (converged) ----
+
+        // ---- tickets: one atomic per wave; ticket i is pool slot i ----
         const bool need = state == NEED_ROOT;
         const unsigned long long mask = __ballot(need);
         if (mask) {
             const int leader = __ffsll((long long)mask) - 1;
             unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(a.qhead, (unsigned long long)__popcll(mask));
+            if (lane == leader) base = atomicAdd(a.head, (unsigned long long)__popcll(mask));
             base = __shfl(base, leader, 64);
             if (need) {
-                const unsigned long long my = base + __popcll(mask & ((1ull << lane) - 1ull));
-                if (my < (unsigned long long)a.nroots) {
-                    const int64_t r = a.order ? a.order[my] : (int64_t)my;
-                    const int8_t *pu = a.roots.u + r * k;
-                    for (int i = L; i < k; ++i) s_u[i * BLOCK + tid] = pu[i];
-                    const double *pw = a.roots.w + r * ws + rot;
-#pragma unroll
-                    for (int j = 0; j < DIMP; j += 2) {
-                        const double2 v = *reinterpret_cast<const double2 *>(pw + j);
-                        w[j] = v.x;
-                        w[j + 1] = v.y;
-                    }
-                    lpar = a.roots.l[r];
-                    tz = a.roots.tz[r];
-                    t = L - 1;
-                    enter_level();
-                    fex = 0;
-                    state = RUN;
-                    ++c_roots;
-                } else {
-                    state = DONE;
+                ticket = (long long)(base + __popcll(mask & lt_mask));
+                state = WAIT;
+            }
+        }
+        // ---- waiting lanes: take the item once its slot is filled ----
+        if (__ballot(state == WAIT)) {
+            bool take = false;
+            if (state == WAIT) {
+                if (ticket < a.nroots) {
+                    take = true;
+                } else if ((phase & 7u) == 3u) {
+                    take = ticket < a.pool.cap && ld_acq(&a.pool.ready[ticket]) != 0;
+                    if (!take && phase == 3u && ld_rlx(a.pending) == 0) state = DONE;
                 }
             }
+            if (take) {
+                const long long it = (ticket < a.nroots && a.order) ? a.order[ticket] : ticket;
+                const int4 mt = a.pool.meta[it];
+                const int T = mt.x;
+                const int8_t *pu = a.pool.u + it * k;
+                for (int j = T + 1; j < k; ++j) my_u[k - 1 - j] = pu[j];
+                // prefix: centres, partial norms and w, top level first
+#pragma unroll
+                for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
+                double l = 0.0;
+                for (int j = k - 1; j > T; --j) {
+                    const double yj = centre_sum(j, k, my_u, s_muc + s_coff[j]);
+                    const double xj = add_rn((double)my_u[k - 1 - j], yj);
+                    l = partial_norm(xj, s_beta[j], l);
+                    const double *gr = a.g_bh + (size_t)j * S + rot;
+#pragma unroll
+                    for (int q = 0; q < DIMP; q += 2) {
+                        const double2 b = *reinterpret_cast<const double2 *>(gr + q);
+                        w[q] = fma(xj, b.x, w[q]);
+                        w[q + 1] = fma(xj, b.y, w[q + 1]);
+                    }
+                }
+                lpar = l;
+                t = T;
+                top = T;
+                tz = (mt.z & F_TZ) ? 1 : 0;
+                bt = s_beta[T];
+                enter_level();
+                if (!(mt.z & F_FRESH)) {
+                    u = mt.y;
+                    onedir = mt.z & F_ONEDIR;
+                    dir = (mt.z & F_DIRPOS) ? 1 : -1;
+                }
+                fex = 0;
+                state = RUN;
+            }
+            if (__ballot(state == RUN) == 0 && __ballot(state == WAIT) != 0)
+                __builtin_amdgcn_s_sleep(32);  // the whole wave is waiting: back off
         }
         if (__ballot(state != DONE) == 0) break;
 
         // ---- control: find this lane's row update ----
-        int kind = K_NONE, row = 0;
+        int kind = K_NONE, row = 0, fin = 0;
         double coef = 0.0;
         unsigned guard = 0;
         while (state == RUN) {
@@ -182,7 +329,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             }
             if (!fex) {
                 const double x = add_rn((double)u, y);
-                const double l = partial_norm(x, s_beta[t], lpar);
+                const double l = partial_norm(x, bt, lpar);
                 ++c_eval;
                 if (l <= a.bound) {  // a NaN norm fails the test and ends the level
                     ++c_node;
@@ -190,26 +337,23 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         ++c_leaf;
                         // exact leaf test (Thm 1) and A x = d, integers only
                         bool ok = true;
-                        int64_t vn = 0;
-                        {
-                            int64_t s = (int64_t)u * a.basis[a.n];
-                            for (int i = 1; i < k; ++i) s += (int64_t)s_u[i * BLOCK + tid] * a.basis[(size_t)i * a.dim + a.n];
-                            vn = s;
-                        }
+                        int64_t vn = (int64_t)u * a.basis[a.n];
+                        for (int i = 1; i < k; ++i) vn += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + a.n];
                         if (vn != 1 && vn != -1) ok = false;
-                        if (ok) {
-                            for (int mi = 0; mi < a.m && ok; ++mi) {
-                                int64_t acc = 0;
-                                for (int j = 0; j < a.n; ++j) {
-                                    int64_t s = (int64_t)u * a.basis[j];
-                                    for (int i = 1; i < k; ++i)
-                                        s += (int64_t)s_u[i * BLOCK + tid] * a.basis[(size_t)i * a.dim + j];
-                                    s *= vn;
-                                    if (s != 1 && s != -1) { ok = false; break; }
-                                    if (s == 1) acc += a.A[(size_t)mi * a.n + j];
+                        for (int mi = 0; mi < a.m && ok; ++mi) {
+                            int64_t acc = 0;
+                            for (int j = 0; j < a.n; ++j) {
+                                int64_t s = (int64_t)u * a.basis[j];
+                                for (int i = 1; i < k; ++i)
+                                    s += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
+                                s *= vn;
+                                if (s != 1 && s != -1) {
+                                    ok = false;
+                                    break;
                                 }
-                                if (ok && acc != a.d[mi]) ok = false;
+                                if (s == 1) acc += a.A[(size_t)mi * a.n + j];
                             }
+                            if (ok && acc != a.d[mi]) ok = false;
                         }
                         if (ok) {
                             const unsigned long long slot = atomicAdd(a.n_found, 1ull);
@@ -218,7 +362,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                                 for (int j = 0; j < a.n; ++j) {
                                     int64_t s = (int64_t)u * a.basis[j];
                                     for (int i = 1; i < k; ++i)
-                                        s += (int64_t)s_u[i * BLOCK + tid] * a.basis[(size_t)i * a.dim + j];
+                                        s += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
                                     xo[j] = (uint8_t)((s * vn + 1) / 2);
                                 }
                             }
@@ -241,8 +385,10 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             }
             fex = 0;
             // level t is exhausted
-            if (t == L - 1) {
+            if (t == top) {
                 state = NEED_ROOT;
+                fin = 1;
+                ++c_items;
                 break;
             }
             if (applied) {
@@ -253,18 +399,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             ++t;
             y = Py;
             lpar = Pl;
-            onedir = Pf & 1;
-            dir = (Pf & 2) ? 1 : -1;
-            tz = (Pf >> 2) & 1;
+            bt = Pbt;
+            u = Pu;
+            onedir = Pf & F_ONEDIR;
+            dir = (Pf & F_DIRPOS) ? 1 : -1;
+            tz = (Pf & F_TZ) ? 1 : 0;
             z = zig_init(y, tz != 0);
-            u = s_u[t * BLOCK + tid];
             u_app = u;
             applied = 1;
-            if (t + 1 <= L - 1) {
+            if (t + 1 <= top) {
                 const double *e = stk + (size_t)(t + 1) * 4;
                 Py = e[0];
                 Pl = e[1];
                 Pf = (int)e[2];
+                Pbt = s_beta[t + 1];
+                Pu = my_u[k - 2 - t];
             }
             advance();
             if (kind == K_REVERT) break;
@@ -306,7 +455,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     atomicOr(&a.flags[0], 1);
                     state = DONE;
                 } else {
-                    if (t + 1 <= L - 1) {
+                    if (t + 1 <= top) {
                         double *e = stk + (size_t)(t + 1) * 4;
                         e[0] = Py;
                         e[1] = Pl;
@@ -314,15 +463,23 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     }
                     Py = y;
                     Pl = lpar;
-                    Pf = onedir | (dir > 0 ? 2 : 0) | (tz << 2);
-                    s_u[t * BLOCK + tid] = (int8_t)u;
+                    Pbt = bt;
+                    Pu = u;
+                    Pf = (onedir ? F_ONEDIR : 0) | (dir > 0 ? F_DIRPOS : 0) | (tz ? F_TZ : 0);
+                    my_u[k - 1 - t] = (int8_t)u;
                     lpar = lcur;
                     tz = (tz && u == 0) ? 1 : 0;
                     --t;
+                    bt = s_beta[t];
                     enter_level();
                 }
             }
         }
+
+        // ---- finished items ----
+        const unsigned long long fm = __ballot(fin != 0);
+        if (fm && lane == (__ffsll((long long)fm) - 1))
+            atomicAdd((unsigned long long *)a.pending, (unsigned long long)(-(long long)__popcll(fm)));
     }
 
     // counters: one atomic per wave
@@ -331,45 +488,58 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         c_node += __shfl_xor(c_node, o, 64);
         c_exp += __shfl_xor(c_exp, o, 64);
         c_leaf += __shfl_xor(c_leaf, o, 64);
-        c_roots += __shfl_xor(c_roots, o, 64);
+        c_items += __shfl_xor(c_items, o, 64);
     }
     if (lane == 0) {
         atomicAdd(&a.counters[0], c_eval);
         atomicAdd(&a.counters[1], c_node);
         atomicAdd(&a.counters[2], c_exp);
         atomicAdd(&a.counters[3], c_leaf);
-        atomicAdd(&a.counters[4], c_roots);
+        atomicAdd(&a.counters[4], c_items);
     }
 }
 
-size_t walk_lds_bytes(int dimp, int block, int k, int L) {
-    const int S = ((dimp + kRotMax + 15) / 16) * 16;
-    return sizeof(double) * ((size_t)L * S + (size_t)k * (k - 1) / 2 + (size_t)((L + 1) & ~1)) +
-           (size_t)k * block;
+hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
+                            double *g_muc, int *g_coff, hipStream_t st) {
+    hipLaunchKernelGGL(walk_prep_kernel, dim3(k), dim3(128), 0, st, k, dim, dimp, bhat, mu, g_bh, g_muc, g_coff);
+    return hipGetLastError();
+}
+
+int walk_muc_len(int k) {
+    int n = 0;
+    for (int t = 0; t < k; ++t) n += ((k - 1 - t + 7) / 8) * 8;
+    return n;
 }
 
 template <int DIMP, int BLOCK>
 static hipError_t launch_one(const WalkArgs &a, int num_cus, hipStream_t st) {
-    const size_t lds = walk_lds_bytes(DIMP, BLOCK, a.k, a.L);
+    const size_t lds = walk_lds_bytes(DIMP, BLOCK, a.k, a.L, a.muc_len);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)walk_kernel<DIMP, BLOCK>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const int per_cu = lds * 2 <= 160 * 1024 ? 2 : 1;
-    hipLaunchKernelGGL((walk_kernel<DIMP, BLOCK>), dim3(num_cus * per_cu), dim3(BLOCK), lds, st, a);
+    hipLaunchKernelGGL((walk_kernel<DIMP, BLOCK>), dim3(num_cus), dim3(BLOCK), lds, st, a);
     return hipGetLastError();
 }
 
+int walk_block_for(int dimp, int k, int L) {
+    const int muc = walk_muc_len(k);
+    if (walk_lds_bytes(dimp, 256, k, L, muc) <= 160 * 1024) return 256;
+    return 0;
+}
+
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st) {
-    if (block != 256) return hipErrorInvalidValue;
+#define MSP_CASE(D)                                                           \
+    case D:                                                                   \
+        if (block == 512 && D <= 88) return launch_one<D, 512>(a, num_cus, st); \
+        if (block == 256) return launch_one<D, 256>(a, num_cus, st);          \
+        return hipErrorInvalidValue;
     switch (dimp) {
-#define MSP_CASE(D) \
-    case D: return launch_one<D, 256>(a, num_cus, st);
         MSP_CASE(24) MSP_CASE(32) MSP_CASE(40) MSP_CASE(48) MSP_CASE(52) MSP_CASE(56) MSP_CASE(64)
         MSP_CASE(72) MSP_CASE(82) MSP_CASE(88) MSP_CASE(96) MSP_CASE(102) MSP_CASE(112) MSP_CASE(128)
-#undef MSP_CASE
         default: return hipErrorInvalidValue;
     }
+#undef MSP_CASE
 }
 
 }  // namespace msp
