@@ -3,8 +3,8 @@
 A thin ctypes layer over ``libmsp.so`` (C ABI in ``include/msp.h``).  The
 functions below carry the C names and only marshal arguments: PyTorch
 tensors supply device memory and the current HIP stream, and every step of
-the method runs in the library's kernels.  There is no CPU fallback: if the
-library is missing, importing this package raises.
+the method runs in the library's kernels.  There is no CPU fallback: the
+library is loaded on first use, and a missing or unloadable library raises.
 """
 from __future__ import annotations
 
@@ -93,20 +93,24 @@ def _load() -> C.CDLL:
     return lib
 
 
-_lib = _load()
+_LIB: C.CDLL | None = None
 
 
 def lib() -> C.CDLL:
-    return _lib
+    """The loaded libmsp (loaded on first call)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
 
 
 def msp_strerror(code: int) -> str:
-    return _lib.msp_strerror(int(code)).decode()
+    return lib().msp_strerror(int(code)).decode()
 
 
 def msp_params_default(**overrides) -> Params:
     p = Params()
-    rc = _lib.msp_params_default(C.byref(p))
+    rc = lib().msp_params_default(C.byref(p))
     if rc != MSP_OK:
         raise MspError(rc, "msp_params_default")
     for key, val in overrides.items():
@@ -135,7 +139,7 @@ class Context:
             raise ValueError("Context needs a GPU device")
         self.device = torch.device("cuda", dev.index if dev.index is not None else 0)
         h = C.c_void_p()
-        rc = _lib.msp_ctx_create(self.device.index, C.byref(h))
+        rc = lib().msp_ctx_create(self.device.index, C.byref(h))
         if rc != MSP_OK:
             raise MspError(rc, "msp_ctx_create")
         self._h = h
@@ -148,7 +152,7 @@ class Context:
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            _lib.msp_ctx_destroy(self._h)
+            lib().msp_ctx_destroy(self._h)
             self._h = None
 
     def __enter__(self):
@@ -181,7 +185,7 @@ def msp_gram_schmidt(ctx: Context, basis: torch.Tensor):
     bhat = torch.empty((k, dim), dtype=torch.float64, device=dev)
     mu = torch.empty((k, k), dtype=torch.float64, device=dev)
     beta = torch.empty((k,), dtype=torch.float64, device=dev)
-    rc = _lib.msp_gram_schmidt(ctx.handle, k, dim, bp, bhat.data_ptr(), mu.data_ptr(), beta.data_ptr(),
+    rc = lib().msp_gram_schmidt(ctx.handle, k, dim, bp, bhat.data_ptr(), mu.data_ptr(), beta.data_ptr(),
                                _stream_handle(dev))
     if rc != MSP_OK:
         raise MspError(rc, "msp_gram_schmidt")
@@ -198,7 +202,7 @@ def msp_reduce(ctx: Context, A: torch.Tensor, d: torch.Tensor, params: Params | 
     basis = torch.zeros((n + 1, n + 1), dtype=torch.int64, device=dev)
     k = C.c_int(0)
     p = params if params is not None else msp_params_default()
-    rc = _lib.msp_reduce(ctx.handle, m, n, ap, dp, C.byref(p), basis.data_ptr(), C.byref(k), _stream_handle(dev))
+    rc = lib().msp_reduce(ctx.handle, m, n, ap, dp, C.byref(p), basis.data_ptr(), C.byref(k), _stream_handle(dev))
     if rc != MSP_OK:
         raise MspError(rc, "msp_reduce")
     return basis[: k.value].contiguous()
@@ -234,7 +238,7 @@ def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.T
     p = params if params is not None else msp_params_default()
     nf = C.c_int64(0)
     st = Stats()
-    rc = _lib.msp_enumerate(ctx.handle, m, n, ap, dp, bp, k, int(mode), int(order), C.byref(p),
+    rc = lib().msp_enumerate(ctx.handle, m, n, ap, dp, bp, k, int(mode), int(order), C.byref(p),
                             out.data_ptr(), int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
     if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
         raise MspError(rc, "msp_enumerate")

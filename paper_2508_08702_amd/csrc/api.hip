@@ -287,8 +287,9 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     const double hfac = 1.0 + p.eps;
 
     // ---- root generation: levels k-1 .. L breadth first ----
-    const int64_t walkers = (int64_t)c->num_cus * 512;  // largest grid of the walk kernel
-    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(4 * walkers, 4096);
+    const int64_t walkers = (int64_t)c->num_cus * 256;  // lanes of the walk kernel
+    // the walker splits work dynamically, so a few roots per lane suffice
+    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(2 * walkers, 4096);
     const int64_t fcap = std::max<int64_t>(4 * target, 1 << 16);
     MSP_TRY(c->fr[0].ensure(fcap, k, ws));
     MSP_TRY(c->fr[1].ensure(fcap, k, ws));
@@ -300,9 +301,12 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     int64_t np = 1;
     int L = k;
     const bool fixed = p.split_depth >= 0;
+    // the walker keeps rows b_hat_0 .. b_hat_{L-1} in LDS: split at least this deep
+    const int L_fit = walk_max_level(dimp, k);
+    if (L_fit < 1) return MSP_E_UNSUPPORTED;
     for (int t = k - 1; t >= 1; --t) {
         if (fixed && k - L >= p.split_depth) break;
-        if (!fixed && np >= target) break;
+        if (!fixed && np >= target && L <= L_fit) break;
         ExpandArgs ea{};
         ea.k = k;
         ea.dim = dim;
@@ -377,6 +381,8 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
         wa.d = d_dev;
         wa.pool = pool;
         wa.nroots = np;
+        wa.root_w = c->fr[cur].w.as<double>();
+        wa.root_l = c->fr[cur].l.as<double>();
         wa.order = nullptr;
         wa.head = &ctl->qhead;
         wa.tail = &ctl->qtail;

@@ -89,6 +89,8 @@ struct WalkArgs {
     const int64_t *d;
     Pool pool;
     int64_t nroots;                // items 0..nroots-1 come from root generation
+    const double *root_w;          // their projected vectors (frontier layout, DIMP + 16 per root)
+    const double *root_l;          // their partial norms
     const int64_t *order;          // optional permutation of those (nullptr = identity)
     unsigned long long *head;      // next ticket
     unsigned long long *tail;      // next free pool slot
@@ -113,6 +115,8 @@ size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len);
 __host__ __device__ int walk_row_stride(int dimp);
 int walk_muc_len(int k);
 int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
+int walk_max_level(int dimp, int k);         // largest split level whose walker fits in LDS
+
 hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
 
 struct LllArgs {

@@ -63,15 +63,23 @@ __device__ __forceinline__ long long ld_rlx(const long long *p) {
 
 // centre sum of level t, top level first (8 levels per chunk).  my_u[p] holds
 // u_{k-1-p}; col[p] = mu_{k-1-p,t}, zero beyond the column's k-1-t entries.
+// The loads of chunk c+1 are issued before chunk c is summed.
 __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, const double *col) {
     const int nt = k - 1 - t;
     double y = 0.0;
+    if (nt <= 0) return y;
+    uint2 uu = *reinterpret_cast<const uint2 *>(my_u);
+    double2 m0 = *reinterpret_cast<const double2 *>(col);
+    double2 m1 = *reinterpret_cast<const double2 *>(col + 2);
+    double2 m2 = *reinterpret_cast<const double2 *>(col + 4);
+    double2 m3 = *reinterpret_cast<const double2 *>(col + 6);
     for (int c = 0; c < nt; c += 8) {
-        const uint2 uu = *reinterpret_cast<const uint2 *>(my_u + c);
-        const double2 m0 = *reinterpret_cast<const double2 *>(col + c);
-        const double2 m1 = *reinterpret_cast<const double2 *>(col + c + 2);
-        const double2 m2 = *reinterpret_cast<const double2 *>(col + c + 4);
-        const double2 m3 = *reinterpret_cast<const double2 *>(col + c + 6);
+        const int cn = c + 8 < nt ? c + 8 : c;  // next chunk (re-read the current one at the end)
+        const uint2 nu = *reinterpret_cast<const uint2 *>(my_u + cn);
+        const double2 n0 = *reinterpret_cast<const double2 *>(col + cn);
+        const double2 n1 = *reinterpret_cast<const double2 *>(col + cn + 2);
+        const double2 n2 = *reinterpret_cast<const double2 *>(col + cn + 4);
+        const double2 n3 = *reinterpret_cast<const double2 *>(col + cn + 6);
         y = add_rn(y, mul_rn((double)(int8_t)(uu.x), m0.x));
         y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 8), m0.y));
         y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 16), m1.x));
@@ -80,6 +88,11 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
         y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 8), m2.y));
         y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 16), m3.x));
         y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 24), m3.y));
+        uu = nu;
+        m0 = n0;
+        m1 = n1;
+        m2 = n2;
+        m3 = n3;
     }
     return y;
 }
@@ -87,7 +100,22 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
 }  // namespace
 
 __host__ __device__ int walk_row_stride(int dimp) { return ((dimp + kRotMax + 15) / 16) * 16; }
-__host__ __device__ int walk_u_stride(int k) { return ((k + 7) / 8) * 8; }
+// per-thread u row: an odd number of 8-byte words, so 16 lanes reading the
+// same word index hit 16 distinct bank pairs
+__host__ __device__ int walk_u_stride(int k) {
+    const int w8 = (k + 7) / 8;
+    return 8 * (w8 | 1);
+}
+// mu column t starts 2 (t mod 8) doubles past a 16-double boundary, so lanes
+// on levels with different t mod 8 read different 16-byte bank groups
+__host__ __device__ int walk_muc_offset(int k, int t) {
+    int off = 0;
+    for (int tt = 0; tt <= t; ++tt) {
+        off = ((off + 15) / 16) * 16 + 2 * (tt & 7);
+        if (tt < t) off += ((k - 1 - tt + 7) / 8) * 8;
+    }
+    return off;
+}
 
 size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len) {
     const int S = walk_row_stride(dimp);
@@ -109,8 +137,7 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
             }
             g_bh[(size_t)t * S + p] = v;
         }
-        int off = 0;
-        for (int tt = 0; tt < t; ++tt) off += ((k - 1 - tt + 7) / 8) * 8;
+        const int off = walk_muc_offset(k, t);
         const int nt = k - 1 - t, np = ((nt + 7) / 8) * 8;
         for (int p = threadIdx.x; p < np; p += blockDim.x)
             g_muc[off + p] = p < nt ? mu[(size_t)(k - 1 - p) * k + t] : 0.0;
@@ -124,9 +151,10 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
 template <int DIMP, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
+    constexpr int kInner = 32;  // iterations of the inner loop between rare-work passes
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k, L = a.L, tid = threadIdx.x;
-    const int KU = ((k + 7) / 8) * 8;
+    const int KU = walk_u_stride(k);
     double *s_bh = reinterpret_cast<double *>(smem);  // L x S
     double *s_muc = s_bh + (size_t)L * S;             // mu columns
     double *s_beta = s_muc + a.muc_len;               // k
@@ -146,20 +174,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     double *stk = a.stack + walker * (int64_t)k * 4;
     int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    const double bound = a.bound, hfac = a.hfac;
+    const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
 
     double w[DIMP];
 #pragma unroll
     for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
 
-    int state = NEED_ROOT, fex = 0;
+    int state = NEED_ROOT, fex = 0, leafpend = 0, fin = 0;
     long long ticket = 0;
     int t = 0, u = 0, onedir = 0, dir = 1, tz = 0, applied = 0, u_app = 0, top = 0;
     Zig z{0, 1};
     double y = 0.0, lpar = 0.0, lcur = 0.0, bt = 1.0;
     double Py = 0.0, Pl = 0.0, Pbt = 1.0;  // cached state of level t+1
-    int Pu = 0, Pf = 0;
+    int Pu = 0, Pf = 0, Pdirty = 0;  // Pdirty: cache differs from stack entry t+1
     unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;
-    unsigned iter = 0;
     unsigned long long t_end = 0;
     if (lane == 0) {
         const unsigned long long t0 = wall_clock();
@@ -178,8 +207,16 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     auto advance = [&]() { u = onedir ? u + dir : zig_next(z, u); };
 
     for (;;) {
-        const unsigned phase = iter++ & 31u;
-        if (phase == 0) {
+        // ================= rare work (at most every kInner iterations) =================
+        // finished items
+        {
+            const unsigned long long fm = __ballot(fin != 0);
+            if (fm && lane == (__ffsll((long long)fm) - 1))
+                atomicAdd((unsigned long long *)a.pending, (unsigned long long)(-(long long)__popcll(fm)));
+            fin = 0;
+        }
+        // stop flag (first hit, time cap, error)
+        {
             int stop = 0;
             if (lane == 0) {
                 stop = ld_acq(&a.flags[0]);
@@ -190,16 +227,61 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 }
             }
             if (__shfl(stop, 0, 64)) state = DONE;
-        } else if (phase == 16) {
-            // ---- donation: split off the untried values of the highest open level,
-            // while lanes hold tickets beyond the last item (head > tail) ----
+        }
+        // exact leaf test (Thm 1) and A x = d, integers only
+        if (__ballot(leafpend != 0)) {
+            if (leafpend && state == RUN) {
+                bool ok = true;
+                int64_t vn = (int64_t)u * a.basis[a.n];
+                for (int i = 1; i < k; ++i) vn += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + a.n];
+                if (vn != 1 && vn != -1) ok = false;
+                for (int mi = 0; mi < a.m && ok; ++mi) {
+                    int64_t acc = 0;
+                    for (int j = 0; j < a.n; ++j) {
+                        int64_t sv = (int64_t)u * a.basis[j];
+                        for (int i = 1; i < k; ++i) sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
+                        sv *= vn;
+                        if (sv != 1 && sv != -1) {
+                            ok = false;
+                            break;
+                        }
+                        if (sv == 1) acc += a.A[(size_t)mi * a.n + j];
+                    }
+                    if (ok && acc != a.d[mi]) ok = false;
+                }
+                if (ok) {
+                    const unsigned long long slot = atomicAdd(a.n_found, 1ull);
+                    if ((int64_t)slot < a.cap) {
+                        uint8_t *xo = a.x_out + (size_t)slot * a.n;
+                        for (int j = 0; j < a.n; ++j) {
+                            int64_t sv = (int64_t)u * a.basis[j];
+                            for (int i = 1; i < k; ++i)
+                                sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
+                            xo[j] = (uint8_t)((sv * vn + 1) / 2);
+                        }
+                    }
+                    if (a.mode == 1) {
+                        atomicCAS(a.t_first, 0ull, wall_clock());
+                        atomicOr(&a.flags[0], 1);
+                    }
+                }
+                advance();
+            }
+            leafpend = 0;
+        }
+        // donation: split off the untried values of the highest open level
+        // while lanes hold tickets beyond the last item (head > tail)
+        {
+            // Every busy lane gives away work at once, which leaves a backlog
+            // and keeps items large; levels below k/6 hold too little work to be
+            // worth the receiver's prefix recomputation.
             int want = 0;
             if (lane == 0) {
                 const unsigned long long h = ld_rlx(a.head), tl = ld_rlx(a.tail);
                 want = h > tl;
             }
             if (__shfl(want, 0, 64)) {
-                bool cand = state == RUN && top > t;
+                bool cand = state == RUN && top > t && top >= k / 6;
                 int D = top, un = 0, fD = 0;
                 if (cand) {
                     double yD, lD, bD;
@@ -216,7 +298,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
                     un = odD ? uD + drD : zig_next(zD, uD);
                     const double l = partial_norm(add_rn((double)un, yD), bD, lD);
-                    if (!(l <= a.bound)) {
+                    if (!(l <= bound)) {
                         // nothing untried left at level D: this is the failing
                         // evaluation that would end level D, so count it here
                         ++c_eval;
@@ -250,29 +332,30 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 }
             }
         }
-
-        // ---- tickets: one atomic per wave; ticket i is pool slot i ----
-        const bool need = state == NEED_ROOT;
-        const unsigned long long mask = __ballot(need);
-        if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(a.head, (unsigned long long)__popcll(mask));
-            base = __shfl(base, leader, 64);
-            if (need) {
-                ticket = (long long)(base + __popcll(mask & lt_mask));
-                state = WAIT;
+        // tickets: one atomic per wave; ticket i is pool slot i
+        {
+            const bool need = state == NEED_ROOT;
+            const unsigned long long mask = __ballot(need);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.head, (unsigned long long)__popcll(mask));
+                base = __shfl(base, leader, 64);
+                if (need) {
+                    ticket = (long long)(base + __popcll(mask & lt_mask));
+                    state = WAIT;
+                }
             }
         }
-        // ---- waiting lanes: take the item once its slot is filled ----
+        // waiting lanes take their item once its slot is filled
         if (__ballot(state == WAIT)) {
             bool take = false;
             if (state == WAIT) {
                 if (ticket < a.nroots) {
                     take = true;
-                } else if ((phase & 7u) == 3u) {
+                } else {
                     take = ticket < a.pool.cap && ld_acq(&a.pool.ready[ticket]) != 0;
-                    if (!take && phase == 3u && ld_rlx(a.pending) == 0) state = DONE;
+                    if (!take && ld_rlx(a.pending) == 0) state = DONE;
                 }
             }
             if (take) {
@@ -280,11 +363,22 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 const int4 mt = a.pool.meta[it];
                 const int T = mt.x;
                 const int8_t *pu = a.pool.u + it * k;
-                for (int j = T + 1; j < k; ++j) my_u[k - 1 - j] = pu[j];
+                for (int j = 0; j < k; ++j) my_u[k - 1 - j] = j > T ? pu[j] : (int8_t)0;
+                double l = 0.0;
+                if (it < a.nroots) {
+                    // a root from root generation: w and its norm are stored
+                    const double *pw = a.root_w + it * (DIMP + kWsTail) + rot;
+#pragma unroll
+                    for (int q = 0; q < DIMP; q += 2) {
+                        const double2 b = *reinterpret_cast<const double2 *>(pw + q);
+                        w[q] = b.x;
+                        w[q + 1] = b.y;
+                    }
+                    l = a.root_l[it];
+                } else {
                 // prefix: centres, partial norms and w, top level first
 #pragma unroll
                 for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
-                double l = 0.0;
                 for (int j = k - 1; j > T; --j) {
                     const double yj = centre_sum(j, k, my_u, s_muc + s_coff[j]);
                     const double xj = add_rn((double)my_u[k - 1 - j], yj);
@@ -296,6 +390,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         w[q] = fma(xj, b.x, w[q]);
                         w[q + 1] = fma(xj, b.y, w[q + 1]);
                     }
+                }
                 }
                 lpar = l;
                 t = T;
@@ -309,177 +404,149 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     dir = (mt.z & F_DIRPOS) ? 1 : -1;
                 }
                 fex = 0;
+                Pdirty = 0;
                 state = RUN;
             }
-            if (__ballot(state == RUN) == 0 && __ballot(state == WAIT) != 0)
-                __builtin_amdgcn_s_sleep(32);  // the whole wave is waiting: back off
         }
         if (__ballot(state != DONE) == 0) break;
+        if (__ballot(state == RUN) == 0) {
+            __builtin_amdgcn_s_sleep(32);  // the whole wave is waiting: back off
+            continue;
+        }
 
-        // ---- control: find this lane's row update ----
-        int kind = K_NONE, row = 0, fin = 0;
-        double coef = 0.0;
-        unsigned guard = 0;
-        while (state == RUN) {
-            if (++guard > (1u << 20)) {  // no valid step sequence is this long: internal error
-                atomicOr(&a.flags[3], 1);
-                atomicOr(&a.flags[0], 1);
-                state = DONE;
-                break;
-            }
-            if (!fex) {
-                const double x = add_rn((double)u, y);
-                const double l = partial_norm(x, bt, lpar);
-                ++c_eval;
-                if (l <= a.bound) {  // a NaN norm fails the test and ends the level
-                    ++c_node;
-                    if (t == 0) {
-                        ++c_leaf;
-                        // exact leaf test (Thm 1) and A x = d, integers only
-                        bool ok = true;
-                        int64_t vn = (int64_t)u * a.basis[a.n];
-                        for (int i = 1; i < k; ++i) vn += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + a.n];
-                        if (vn != 1 && vn != -1) ok = false;
-                        for (int mi = 0; mi < a.m && ok; ++mi) {
-                            int64_t acc = 0;
-                            for (int j = 0; j < a.n; ++j) {
-                                int64_t s = (int64_t)u * a.basis[j];
-                                for (int i = 1; i < k; ++i)
-                                    s += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                                s *= vn;
-                                if (s != 1 && s != -1) {
-                                    ok = false;
-                                    break;
-                                }
-                                if (s == 1) acc += a.A[(size_t)mi * a.n + j];
-                            }
-                            if (ok && acc != a.d[mi]) ok = false;
+        // ================= inner loop: one row update per lane per iteration =================
+#pragma unroll 1
+        for (int it = 0; it < kInner; ++it) {
+            // ---- control: at most two evaluations and one pop ----
+            int kind = K_NONE, row = 0;
+            double coef = 0.0;
+            bool popped = false;
+            while (state == RUN) {
+                if (!fex) {
+                    const double x = add_rn((double)u, y);
+                    const double l = partial_norm(x, bt, lpar);
+                    ++c_eval;
+                    if (l <= bound) {  // a NaN norm fails the test and ends the level
+                        ++c_node;
+                        if (t == 0) {  // a leaf: checked exactly in the rare-work pass
+                            ++c_leaf;
+                            leafpend = 1;
+                            break;
                         }
-                        if (ok) {
-                            const unsigned long long slot = atomicAdd(a.n_found, 1ull);
-                            if ((int64_t)slot < a.cap) {
-                                uint8_t *xo = a.x_out + (size_t)slot * a.n;
-                                for (int j = 0; j < a.n; ++j) {
-                                    int64_t s = (int64_t)u * a.basis[j];
-                                    for (int i = 1; i < k; ++i)
-                                        s += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                                    xo[j] = (uint8_t)((s * vn + 1) / 2);
-                                }
-                            }
-                            if (a.mode == 1) {
-                                atomicCAS(a.t_first, 0ull, wall_clock());
-                                atomicOr(&a.flags[0], 1);
-                            }
-                        }
-                        advance();
-                        continue;
+                        kind = K_NODE;
+                        row = t;
+                        coef = applied ? (double)(u - u_app) : x;
+                        u_app = u;
+                        applied = 1;
+                        lcur = l;
+                        break;
                     }
-                    kind = K_NODE;
-                    row = t;
-                    coef = applied ? (double)(u - u_app) : x;
-                    u_app = u;
-                    applied = 1;
-                    lcur = l;
+                }
+                fex = 0;
+                // level t is exhausted
+                if (t == top) {
+                    state = NEED_ROOT;
+                    fin = 1;
+                    ++c_items;
                     break;
                 }
-            }
-            fex = 0;
-            // level t is exhausted
-            if (t == top) {
-                state = NEED_ROOT;
-                fin = 1;
-                ++c_items;
-                break;
-            }
-            if (applied) {
-                kind = K_REVERT;
-                row = t;
-                coef = -add_rn((double)u_app, y);
-            }
-            ++t;
-            y = Py;
-            lpar = Pl;
-            bt = Pbt;
-            u = Pu;
-            onedir = Pf & F_ONEDIR;
-            dir = (Pf & F_DIRPOS) ? 1 : -1;
-            tz = (Pf & F_TZ) ? 1 : 0;
-            z = zig_init(y, tz != 0);
-            u_app = u;
-            applied = 1;
-            if (t + 1 <= top) {
-                const double *e = stk + (size_t)(t + 1) * 4;
-                Py = e[0];
-                Pl = e[1];
-                Pf = (int)e[2];
-                Pbt = s_beta[t + 1];
-                Pu = my_u[k - 2 - t];
-            }
-            advance();
-            if (kind == K_REVERT) break;
-        }
-
-        // ---- the row update, all lanes together ----
-        double h = 0.0;
-        if (__ballot(kind != K_NONE)) {
-            const double *br = s_bh + (size_t)row * S + rot;
-            double h0 = 0.0, h1 = 0.0;
-#pragma unroll
-            for (int j = 0; j < DIMP; j += 2) {
-                const double2 b = *reinterpret_cast<const double2 *>(br + j);
-                w[j] = fma(coef, b.x, w[j]);
-                w[j + 1] = fma(coef, b.y, w[j + 1]);
-                h0 += fabs(w[j]);
-                h1 += fabs(w[j + 1]);
-            }
-            h = h0 + h1;
-        }
-
-        // ---- Hoelder test and the step that follows ----
-        if (kind == K_NODE) {
-            const bool fail = a.hoelder && (lcur > h * a.hfac);
-            if (fail) {
-                if (!a.onedir) {
-                    advance();
-                } else if (onedir) {
+                if (popped) {
+                    // a second pop would wait for the level state the first pop is
+                    // still fetching: pop in the next iteration instead
                     fex = 1;
-                } else {
-                    u = zig_next(z, u);
-                    onedir = 1;
-                    dir = side_of(u, y);
+                    break;
                 }
-            } else {
-                ++c_exp;
-                if (u > 127 || u < -127) {
-                    atomicOr(&a.flags[1], 1);
-                    atomicOr(&a.flags[0], 1);
-                    state = DONE;
-                } else {
-                    if (t + 1 <= top) {
-                        double *e = stk + (size_t)(t + 1) * 4;
-                        e[0] = Py;
-                        e[1] = Pl;
-                        e[2] = (double)Pf;
+                if (applied) {
+                    kind = K_REVERT;
+                    row = t;
+                    coef = -add_rn((double)u_app, y);
+                }
+                ++t;
+                y = Py;
+                lpar = Pl;
+                bt = Pbt;
+                u = Pu;
+                onedir = Pf & F_ONEDIR;
+                dir = (Pf & F_DIRPOS) ? 1 : -1;
+                tz = (Pf & F_TZ) ? 1 : 0;
+                z = zig_init(y, tz != 0);
+                u_app = u;
+                applied = 1;
+                if (t + 1 <= top) {
+                    const double *e = stk + (size_t)(t + 1) * 4;
+                    Py = e[0];
+                    Pl = e[1];
+                    Pf = (int)e[2];
+                    Pbt = s_beta[t + 1];
+                    Pu = my_u[k - 2 - t];
+                    Pdirty = 0;
+                }
+                advance();
+                popped = true;
+                if (kind == K_REVERT) break;
+            }
+
+            // ---- the row update, all lanes together ----
+            double h = 0.0;
+            if (__ballot(kind != K_NONE)) {
+                const double *br = s_bh + (size_t)row * S + rot;
+                double h0 = 0.0, h1 = 0.0;
+#pragma unroll
+                for (int j = 0; j < DIMP; j += 2) {
+                    const double2 b = *reinterpret_cast<const double2 *>(br + j);
+                    w[j] = fma(coef, b.x, w[j]);
+                    w[j + 1] = fma(coef, b.y, w[j + 1]);
+                    h0 += fabs(w[j]);
+                    h1 += fabs(w[j + 1]);
+                }
+                h = h0 + h1;
+            }
+
+            // ---- Hoelder test and the step that follows ----
+            if (kind == K_NODE) {
+                const bool fail = hoelder && (lcur > h * hfac);
+                if (fail) {
+                    if (!onedir_cut) {
+                        advance();
+                    } else if (onedir) {
+                        fex = 1;
+                    } else {
+                        u = zig_next(z, u);
+                        onedir = 1;
+                        dir = side_of(u, y);
                     }
-                    Py = y;
-                    Pl = lpar;
-                    Pbt = bt;
-                    Pu = u;
-                    Pf = (onedir ? F_ONEDIR : 0) | (dir > 0 ? F_DIRPOS : 0) | (tz ? F_TZ : 0);
-                    my_u[k - 1 - t] = (int8_t)u;
-                    lpar = lcur;
-                    tz = (tz && u == 0) ? 1 : 0;
-                    --t;
-                    bt = s_beta[t];
-                    enter_level();
+                } else {
+                    ++c_exp;
+                    if (u > 127 || u < -127) {
+                        atomicOr(&a.flags[1], 1);
+                        atomicOr(&a.flags[0], 1);
+                        state = DONE;
+                    } else {
+                        if (Pdirty && t + 1 <= top) {  // only a level first cached here needs writing
+                            double *e = stk + (size_t)(t + 1) * 4;
+                            e[0] = Py;
+                            e[1] = Pl;
+                            e[2] = (double)Pf;
+                        }
+                        Pdirty = 1;
+                        Py = y;
+                        Pl = lpar;
+                        Pbt = bt;
+                        Pu = u;
+                        Pf = (onedir ? F_ONEDIR : 0) | (dir > 0 ? F_DIRPOS : 0) | (tz ? F_TZ : 0);
+                        my_u[k - 1 - t] = (int8_t)u;
+                        lpar = lcur;
+                        tz = (tz && u == 0) ? 1 : 0;
+                        --t;
+                        bt = s_beta[t];
+                        enter_level();
+                    }
                 }
             }
+            // leave for the rare-work pass when some lane needs it (waiting lanes
+            // are served there too, but only every kInner iterations)
+            if (__ballot(state == NEED_ROOT || leafpend != 0) || !__ballot(state == RUN)) break;
         }
-
-        // ---- finished items ----
-        const unsigned long long fm = __ballot(fin != 0);
-        if (fm && lane == (__ffsll((long long)fm) - 1))
-            atomicAdd((unsigned long long *)a.pending, (unsigned long long)(-(long long)__popcll(fm)));
     }
 
     // counters: one atomic per wave
@@ -505,11 +572,7 @@ hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const 
     return hipGetLastError();
 }
 
-int walk_muc_len(int k) {
-    int n = 0;
-    for (int t = 0; t < k; ++t) n += ((k - 1 - t + 7) / 8) * 8;
-    return n;
-}
+int walk_muc_len(int k) { return walk_muc_offset(k, k - 1) + 8; }
 
 template <int DIMP, int BLOCK>
 static hipError_t launch_one(const WalkArgs &a, int num_cus, hipStream_t st) {
@@ -522,10 +585,14 @@ static hipError_t launch_one(const WalkArgs &a, int num_cus, hipStream_t st) {
     return hipGetLastError();
 }
 
-int walk_block_for(int dimp, int k, int L) {
-    const int muc = walk_muc_len(k);
-    if (walk_lds_bytes(dimp, 256, k, L, muc) <= 160 * 1024) return 256;
+int walk_max_level(int dimp, int k) {
+    for (int L = k; L >= 1; --L)
+        if (walk_lds_bytes(dimp, 256, k, L, walk_muc_len(k)) <= 160 * 1024) return L;
     return 0;
+}
+
+int walk_block_for(int dimp, int k, int L) {
+    return walk_lds_bytes(dimp, 256, k, L, walk_muc_len(k)) <= 160 * 1024 ? 256 : 0;
 }
 
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st) {
