@@ -144,6 +144,24 @@ int msp_enumerate(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_
                   const int64_t *basis_dev, int k, int mode, int order, const msp_params *p,
                   uint8_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats, void *stream);
 
+/* One instance of a batch: A_dev + A_off holds its m x n matrix, d_dev +
+ * d_off its right-hand side, x_dev + x_off its output rows (cap x n). */
+typedef struct {
+    int32_t m, n;
+    int64_t A_off, d_off, x_off, cap;
+} msp_batch_desc;
+
+/* Reduce and enumerate a batch of independent instances of uneven shape
+ * (Sections 1-2): one LLL launch reduces every instance (one wave each),
+ * then each instance is enumerated as by msp_enumerate on its own basis.
+ * desc: host array of `batch` descriptors (offsets in elements).  Outputs
+ * (host arrays of length batch): n_found[i], status[i] (an MSP_* code per
+ * instance), stats[i] (may be NULL).  Returns MSP_OK when every instance
+ * returned MSP_OK, otherwise the first non-OK instance status. */
+int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const int32_t *A_dev,
+                    const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
+                    int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *msp_strerror(int code);
 

@@ -38,7 +38,7 @@ MSP_MAX_N = 127
 # every symbol include/msp.h declares
 EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
-    "msp_gram_schmidt", "msp_enumerate", "msp_strerror",
+    "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_strerror",
 )
 
 
@@ -70,6 +70,11 @@ class Stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchDesc(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("A_off", C.c_int64), ("d_off", C.c_int64),
+                ("x_off", C.c_int64), ("cap", C.c_int64)]
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_08702_amd.build`")
@@ -88,6 +93,9 @@ def _load() -> C.CDLL:
     lib.msp_enumerate.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, i64,
                                   C.POINTER(i64), C.POINTER(Stats), vp]
     lib.msp_enumerate.restype = i32
+    lib.msp_solve_batch.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params), vp,
+                                    C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(Stats), vp]
+    lib.msp_solve_batch.restype = i32
     lib.msp_strerror.argtypes = [i32]
     lib.msp_strerror.restype = C.c_char_p
     return lib
@@ -244,3 +252,53 @@ def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.T
         raise MspError(rc, "msp_enumerate")
     rows = min(nf.value, cap)
     return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())
+
+
+@dataclass
+class BatchResult:
+    x: list           # per instance: uint8 (rows, n) device tensor (views into one packed buffer)
+    n_found: list     # per instance
+    status: list      # per instance MSP_* code
+    stats: list       # per instance dict
+    rc: int           # MSP_OK, or the first non-OK instance status
+
+
+def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order: int = MSP_PLAIN,
+                    params: Params | None = None, cap: int = 1024) -> BatchResult:
+    """Reduce and enumerate a batch of instances of uneven shape.
+
+    As / ds: lists of int32 (m_i x n_i) and int64 (m_i) device tensors.  They
+    are packed into one buffer each (plain device copies) and described to
+    the library by element offsets; every instance gets ``cap`` output rows."""
+    if len(As) != len(ds) or not As:
+        raise ValueError("As and ds must be non-empty lists of equal length")
+    dev = ctx.device
+    for i, (A, d) in enumerate(zip(As, ds)):
+        _dev_ptr(A, torch.int32, dev, f"As[{i}]")
+        _dev_ptr(d, torch.int64, dev, f"ds[{i}]")
+    b = len(As)
+    desc = (BatchDesc * b)()
+    a_off = d_off = x_off = 0
+    for i, A in enumerate(As):
+        m, n = A.shape
+        desc[i] = BatchDesc(m, n, a_off, d_off, x_off, cap)
+        a_off += m * n
+        d_off += m
+        x_off += cap * n
+    A_all = torch.cat([A.reshape(-1) for A in As])
+    d_all = torch.cat([d.reshape(-1) for d in ds])
+    x_all = torch.zeros(max(x_off, 1), dtype=torch.uint8, device=dev)
+    nf = (C.c_int64 * b)()
+    st = (C.c_int32 * b)()
+    stats = (Stats * b)()
+    p = params if params is not None else msp_params_default()
+    rc = lib().msp_solve_batch(ctx.handle, b, desc, A_all.data_ptr(), d_all.data_ptr(), int(mode), int(order),
+                               C.byref(p), x_all.data_ptr(), nf, st, stats, _stream_handle(dev))
+    if rc == MSP_E_ARG or rc == MSP_E_DEVICE or rc == MSP_E_NOMEM:
+        raise MspError(rc, "msp_solve_batch")
+    xs = []
+    for i in range(b):
+        n = desc[i].n
+        rows = min(nf[i], cap)
+        xs.append(x_all[desc[i].x_off: desc[i].x_off + cap * n].view(cap, n)[:rows])
+    return BatchResult(x=xs, n_found=list(nf), status=list(st), stats=[s.as_dict() for s in stats], rc=rc)

@@ -98,7 +98,7 @@ struct msp_ctx {
     Buf stack;
     Buf ctl;
     Buf order;
-    Buf lll_desc, lll_work;
+    Buf lll_desc, lll_work, batch_basis;
     Buf g_bh, g_muc, g_coff;
     Buf pool_u, pool_meta, pool_ready;
     long long last_lll_iters = 0;
@@ -218,6 +218,7 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->order.release();
     c->lll_desc.release();
     c->lll_work.release();
+    c->batch_basis.release();
     c->g_bh.release();
     c->g_muc.release();
     c->g_coff.release();
@@ -245,9 +246,11 @@ int msp_gram_schmidt(msp_ctx *c, int k, int dim, const int64_t *basis_dev, doubl
     return err ? MSP_E_NUMERIC : MSP_OK;
 }
 
-int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
-                  int k, int mode, int order, const msp_params *pin, uint8_t *x_dev, int64_t cap, int64_t *n_found,
-                  msp_stats *stats, void *stream) {
+}  // extern "C"
+
+static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                          const int64_t *basis_dev, int k, int mode, int order, const msp_params *pin, uint8_t *x_dev,
+                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream) {
     auto t_call = std::chrono::steady_clock::now();
     if (!c || !A_dev || !d_dev || !basis_dev || !n_found || (cap > 0 && !x_dev) || cap < 0) return MSP_E_ARG;
     if (m < 1 || n < 1 || m > n || n > MSP_MAX_N || k != n - m + 1) return MSP_E_ARG;
@@ -438,31 +441,50 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
     return MSP_OK;
 }
 
-int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *pin,
-               int64_t *basis_dev, int *k_out, void *stream) {
-    if (!c || !A_dev || !d_dev || !basis_dev || !k_out) return MSP_E_ARG;
-    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
-    msp_params p;
-    msp_params_default(&p);
-    if (pin) p = *pin;
-    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
-    *k_out = 0;
-    DeviceGuard g(c->device);
-    hipStream_t st = (hipStream_t)stream;
-    const int nv = n + 1, len = m + n + 1;
-    // one-instance descriptor block: m, n | A_off, d_off, work_off, out_off | status, kout | iters
-    struct Desc {
-        int m, n;
-        int64_t A_off, d_off, work_off, out_off;
-        int32_t status, kout;
-        long long iters;
-    };
-    MSP_TRY(c->lll_desc.ensure(sizeof(Desc)));
-    MSP_TRY(c->lll_work.ensure((size_t)nv * len * sizeof(long long)));
-    Desc h{m, n, 0, 0, 0, 0, 0, 0, 0};
-    Desc *dd = c->lll_desc.as<Desc>();
-    MSP_TRY(hipMemcpyAsync(dd, &h, sizeof(Desc), hipMemcpyHostToDevice, st));
+extern "C" {
+
+int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
+                  int k, int mode, int order, const msp_params *p, uint8_t *x_dev, int64_t cap, int64_t *n_found,
+                  msp_stats *stats, void *stream) {
+    return enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, mode, order, p, x_dev, cap, n_found, stats, stream);
+}
+
+namespace {
+// per-instance descriptor of a reduction launch
+struct LllDesc {
+    int m, n;
+    int64_t A_off, d_off, work_off, out_off;
+    int32_t status, kout;
+    long long iters;
+};
+
+int lll_status(int32_t st) {
+    switch (st) {
+        case 0: return MSP_OK;
+        case -2: return MSP_E_RANK;
+        case -3: return MSP_E_NOT_ISOLATED;
+        case -4: return MSP_E_OVERFLOW;
+        default: return MSP_E_NUMERIC;
+    }
+}
+
+// One launch reduces `cnt` instances; descriptors are copied to the device.
+int run_lll(msp_ctx *c, std::vector<LllDesc> &h, const int32_t *A_dev, const int64_t *d_dev, int64_t *out,
+            const msp_params &p, hipStream_t st) {
+    const int cnt = (int)h.size();
+    int maxn = 0;
+    size_t work = 0;
+    for (auto &e : h) {
+        maxn = std::max(maxn, e.n);
+        e.work_off = (int64_t)work;
+        work += (size_t)(e.n + 1) * (e.m + e.n + 1);
+    }
+    MSP_TRY(c->lll_desc.ensure(sizeof(LllDesc) * cnt));
+    MSP_TRY(c->lll_work.ensure(work * sizeof(long long)));
+    LllDesc *dd = c->lll_desc.as<LllDesc>();
+    MSP_TRY(hipMemcpyAsync(dd, h.data(), sizeof(LllDesc) * cnt, hipMemcpyHostToDevice, st));
     LllArgs la{};
+    // the kernel reads every per-instance field through these strided views
     la.m = &dd->m;
     la.n = &dd->n;
     la.A = A_dev;
@@ -474,22 +496,87 @@ int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_
     la.max_iters = 2000000;
     la.work = c->lll_work.as<long long>();
     la.work_off = &dd->work_off;
-    la.out = basis_dev;
+    la.out = out;
     la.out_off = &dd->out_off;
     la.status = &dd->status;
     la.kout = &dd->kout;
     la.iters = &dd->iters;
-    MSP_TRY(launch_lll(la, 1, n, st));
-    MSP_TRY(hipMemcpyAsync(&h, dd, sizeof(Desc), hipMemcpyDeviceToHost, st));
+    la.stride = (int)(sizeof(LllDesc) / sizeof(int32_t));
+    MSP_TRY(launch_lll(la, cnt, maxn, st));
+    MSP_TRY(hipMemcpyAsync(h.data(), dd, sizeof(LllDesc) * cnt, hipMemcpyDeviceToHost, st));
     MSP_TRY(hipStreamSynchronize(st));
-    c->last_lll_iters = h.iters;
-    switch (h.status) {
-        case 0: *k_out = h.kout; return MSP_OK;
-        case -2: return MSP_E_RANK;
-        case -3: return MSP_E_NOT_ISOLATED;
-        case -4: return MSP_E_OVERFLOW;
-        default: return MSP_E_NUMERIC;
+    return MSP_OK;
+}
+}  // namespace
+
+int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *pin,
+               int64_t *basis_dev, int *k_out, void *stream) {
+    if (!c || !A_dev || !d_dev || !basis_dev || !k_out) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    *k_out = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<LllDesc> h(1);
+    h[0] = LllDesc{m, n, 0, 0, 0, 0, 0, 0, 0};
+    const int rc = run_lll(c, h, A_dev, d_dev, basis_dev, p, st);
+    if (rc != MSP_OK) return rc;
+    c->last_lll_iters = h[0].iters;
+    const int s = lll_status(h[0].status);
+    if (s == MSP_OK) *k_out = h[0].kout;
+    return s;
+}
+
+int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,
+                    int mode, int order, const msp_params *pin, uint8_t *x_dev, int64_t *n_found, int32_t *status,
+                    msp_stats *stats, void *stream) {
+    if (!c || batch < 1 || !desc || !A_dev || !d_dev || !n_found || !status) return MSP_E_ARG;
+    for (int i = 0; i < batch; ++i) {
+        const msp_batch_desc &e = desc[i];
+        if (e.m < 1 || e.n < 1 || e.m > e.n || e.n > MSP_MAX_N || e.A_off < 0 || e.d_off < 0 || e.x_off < 0 ||
+            e.cap < 0 || (e.cap > 0 && !x_dev))
+            return MSP_E_ARG;
     }
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    // ---- steps 1-2 for the whole batch in one launch ----
+    std::vector<LllDesc> h(batch);
+    size_t boff = 0;
+    for (int i = 0; i < batch; ++i) {
+        h[i] = LllDesc{desc[i].m, desc[i].n, desc[i].A_off, desc[i].d_off, 0, (int64_t)boff, 0, 0, 0};
+        boff += (size_t)(desc[i].n + 1) * (desc[i].n + 1);
+    }
+    MSP_TRY(c->batch_basis.ensure(boff * sizeof(int64_t)));
+    int64_t *bases = c->batch_basis.as<int64_t>();
+    int rc = run_lll(c, h, A_dev, d_dev, bases, p, st);
+    if (rc != MSP_OK) return rc;
+    const double reduce_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / batch;
+    // ---- steps 3-4 per instance ----
+    int first_bad = MSP_OK;
+    for (int i = 0; i < batch; ++i) {
+        const msp_batch_desc &e = desc[i];
+        n_found[i] = 0;
+        int s = lll_status(h[i].status);
+        msp_stats sti;
+        std::memset(&sti, 0, sizeof(sti));
+        if (s == MSP_OK)
+            s = enumerate_impl(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off, h[i].kout, mode,
+                               order, &p, x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream);
+        sti.reduce_ms = reduce_ms;
+        status[i] = s;
+        if (stats) stats[i] = sti;
+        if (s != MSP_OK && first_bad == MSP_OK) first_bad = s;
+    }
+    return first_bad;
 }
 
 }  // extern "C"

@@ -36,11 +36,18 @@ __device__ __forceinline__ long long gram_at(const long long *G, int i, int j) {
 
 __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     const int inst = blockIdx.x;
-    const int m = a.m[inst], n = a.n[inst];
+    const size_t si = (size_t)inst * a.stride;  // 4-byte units
+    const int m = a.m[si], n = a.n[si];
     const int nv = n + 1, len = m + n + 1;
     const int lane = threadIdx.x;
-    long long *B = a.work + a.work_off[inst];            // nv x len
-    int32_t *status = a.status + inst;
+    const int64_t A_off = *reinterpret_cast<const int64_t *>(reinterpret_cast<const int32_t *>(a.A_off) + si);
+    const int64_t d_off = *reinterpret_cast<const int64_t *>(reinterpret_cast<const int32_t *>(a.d_off) + si);
+    const int64_t w_off = *reinterpret_cast<const int64_t *>(reinterpret_cast<const int32_t *>(a.work_off) + si);
+    const int64_t o_off = *reinterpret_cast<const int64_t *>(reinterpret_cast<const int32_t *>(a.out_off) + si);
+    long long *B = a.work + w_off;                       // nv x len
+    int32_t *status = a.status + si;
+    int32_t *kout = a.kout + si;
+    long long *iters_out = reinterpret_cast<long long *>(reinterpret_cast<int32_t *>(a.iters) + si);
     extern __shared__ __align__(16) unsigned char smem[];
     long long *G = reinterpret_cast<long long *>(smem);  // nv(nv+1)/2
     double *mu = reinterpret_cast<double *>(G + nv * (nv + 1) / 2);  // nv(nv-1)/2, row k at k(k-1)/2
@@ -48,8 +55,8 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     double *rr = Bn + nv;                                // nv scratch: r_kj of the current row
     int *sflag = reinterpret_cast<int *>(rr + nv);       // [0] overflow
 
-    const int32_t *A = a.A + a.A_off[inst];
-    const int64_t *d = a.d + a.d_off[inst];
+    const int32_t *A = a.A + A_off;
+    const int64_t *d = a.d + d_off;
     const long long N = a.N;
 
     // ---- eq. (2): vector 0 = (-N d; -1 x n; 1), vector j = (N a_j; 2 e_j; 0)
@@ -80,8 +87,8 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     if (sflag[0]) {
         if (lane == 0) {
             status[0] = -4;
-            a.kout[inst] = 0;
-            a.iters[inst] = 0;
+            kout[0] = 0;
+            iters_out[0] = 0;
         }
         return;
     }
@@ -242,7 +249,7 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
             const bool allzero = __ballot(!zero) == 0;
             if (allzero) {
                 if (count < kexp) {
-                    int64_t *out = a.out + a.out_off[inst] + (size_t)count * (n + 1);
+                    int64_t *out = a.out + o_off + (size_t)count * (n + 1);
                     for (int c4 = 0; c4 < kMaxCols; ++c4) {
                         const int c = lane + c4 * kLanes;
                         if (c >= m && c < len) out[c - m] = B[(size_t)r * len + c];
@@ -256,8 +263,8 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     }
     if (lane == 0) {
         status[0] = st;
-        a.kout[inst] = count;
-        a.iters[inst] = iters;
+        kout[0] = count;
+        iters_out[0] = iters;
     }
 }
 

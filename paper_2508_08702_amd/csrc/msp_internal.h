@@ -119,6 +119,8 @@ int walk_max_level(int dimp, int k);         // largest split level whose walker
 
 hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
 
+// Per-instance fields are read as base[i * stride] (in 4-byte units), so a
+// packed array of descriptor structs serves as the per-instance arrays.
 struct LllArgs {
     const int *m, *n;              // per instance
     const int32_t *A;              // packed instances; A of instance i at A + A_off[i] (m x n)
@@ -135,6 +137,7 @@ struct LllArgs {
     int32_t *status;               // 0, -2 (rank), -3 (not isolated), -4 (overflow), -10 (no convergence)
     int32_t *kout;                 // zero-top vectors found
     long long *iters;              // LLL iterations used
+    int stride;                    // distance between instances, in 4-byte units
 };
 hipError_t launch_lll(const LllArgs &a, int ninst, int max_n, hipStream_t st);
 size_t lll_lds_bytes(int n);
