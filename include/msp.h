@@ -59,8 +59,24 @@ enum {
 
 /* enumeration modes */
 enum { MSP_ALL = 0, MSP_FIRST = 1 };
-/* subtree root orders for MSP_FIRST (MSP_ALL ignores the order) */
-enum { MSP_PLAIN = 0, MSP_LEARNED = 1 };
+/* Orders in which the subtree roots are walked.  The order changes only
+ * which solutions MSP_FIRST meets first and how soon; MSP_ALL returns the same
+ * set and the same search-tree counters in every order.
+ *   MSP_PLAIN        depth-first order (the order of Algorithm 1)
+ *   MSP_LEARNED      best score first under the context's root-scoring model
+ *                    (msp_model_init / msp_model_set / msp_model_train)
+ *   MSP_DISCREPANCY  fewest discrepancies first -- roots whose prefix departs
+ *                    least often from each level's first zig-zag value -- then
+ *                    depth-first: limited discrepancy search (Section 3)
+ *                    applied to the roots */
+enum { MSP_PLAIN = 0, MSP_LEARNED = 1, MSP_DISCREPANCY = 2 };
+
+/* Root-scoring model: features per root and parameters of the MLP
+ * 16 -> 64 -> 64 -> 1 (ReLU), used with BF16-rounded weights and FP32
+ * accumulation.  Parameter vector layout (floats):
+ *   W1[64][16] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3. */
+#define MSP_NFEAT 16
+#define MSP_MODEL_NPARAM 5313
 
 typedef struct msp_ctx msp_ctx;
 
@@ -92,9 +108,10 @@ typedef struct {
     double reduce_ms;        /* msp_reduce (embedding + LLL + extraction)        */
     double gs_ms;            /* Gram-Schmidt kernel                              */
     double rootgen_ms;       /* root generation (levels above the split)         */
-    double ordering_ms;      /* root scoring and sort (learned order only)       */
+    double ordering_ms;      /* root features, scores and sort (non-plain orders) */
     double kernel_ms;        /* walk kernel                                      */
-    double ttfs_ms;          /* MSP_FIRST: walk-kernel start to first verified hit; -1 if none */
+    double ttfs_ms;          /* MSP_FIRST: ordering_ms + walk-kernel start to the
+                              * first verified hit (device clock); -1 if none   */
     double total_ms;         /* whole call                                       */
 } msp_stats;
 
@@ -133,8 +150,8 @@ int msp_gram_schmidt(msp_ctx *ctx, int k, int dim, const int64_t *basis_dev,
  * A x = d in integers).
  * mode MSP_ALL returns every solution exactly once (unspecified order);
  * MSP_FIRST stops at the first verified solution (one or a few rows).
- * order: MSP_PLAIN (depth-first root order) or MSP_LEARNED (roots sorted by
- * the context's root-scoring model; needs msp_set_order_model first).
+ * order: MSP_PLAIN, MSP_LEARNED (needs a model: MSP_E_ARG otherwise) or
+ * MSP_DISCREPANCY; see above.
  * x_dev: uint8 cap x n, rows of 0/1.  *n_found: solutions found (may exceed
  * cap: then only cap rows are written and MSP_E_CAPACITY is returned after the
  * full enumeration).  stats may be NULL.
@@ -161,6 +178,63 @@ typedef struct {
 int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const int32_t *A_dev,
                     const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
                     int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
+
+/* ---- root traces and the root-scoring model (a project addition; none of
+ * this is in the paper) ------------------------------------------------- */
+
+/* Exhaustive msp_enumerate (MSP_ALL, plain order) that also returns, for
+ * every subtree root at the split level, MSP_NFEAT features (feat_dev, FP32
+ * row-major, cap_roots x MSP_NFEAT) and a label (label_dev, uint8: 1 iff a
+ * solution lies in that root's subtree).  Features of root r at level L with
+ * prefix u_{k-1..L}, partial norm l, projected vector w (R = n+1):
+ *   0 l/R   1 l/||w||_1   2 min(||w||_inf,4)/4   3 mean zig-zag rank of u_j
+ *   4 fraction of levels with rank > 0   5 min(max rank,8)/8
+ *   6 fraction of u_j != 0   7 mean |u_j|   8 min(max|u_j|,4)/4
+ *   9 x_L^2 beta_L / R   10 min(|x_L|,2)/2   11 (L/k) ln(max((R-l)/R,1e-6))/8
+ *   12 r / roots   13 fraction of |w_j| > 17/16   14 L/k   15 m/16
+ * (rank of u_j = its position in level j's zig-zag sequence; u_j itself while
+ * all higher u are 0).  *nroots = root count, *n_found = solutions.
+ * Errors: those of msp_enumerate; MSP_E_CAPACITY if roots > cap_roots (only
+ * *nroots is set) or more than 65536 solutions (labels incomplete). */
+int msp_root_trace(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                   const int64_t *basis_dev, int k, const msp_params *p, float *feat_dev,
+                   uint8_t *label_dev, int64_t cap_roots, int64_t *nroots, int64_t *n_found,
+                   msp_stats *stats, void *stream);
+
+/* Model weights (host arrays of MSP_MODEL_NPARAM floats, FP32 master copy).
+ * msp_model_init: He-normal hidden weights, N(0,1/64) output weights, zero
+ * biases, from `seed`.  msp_model_set rejects non-finite values (MSP_E_ARG).
+ * msp_model_get: MSP_E_ARG if no model was set. */
+int msp_model_init(msp_ctx *ctx, uint64_t seed);
+int msp_model_set(msp_ctx *ctx, const float *w);
+int msp_model_get(msp_ctx *ctx, float *w);
+
+/* logit_dev[i] = model score of feature row i (count rows, device arrays). */
+int msp_model_score(msp_ctx *ctx, const float *feat_dev, int64_t count, float *logit_dev, void *stream);
+
+/* Gradient (grad_dev, MSP_MODEL_NPARAM floats, device) and value (*loss,
+ * host) of the weighted logistic loss over all `count` rows:
+ *   loss = (1/count) sum_i c_i (softplus(z_i) - y_i z_i),
+ *   c_i = pos_weight if label_i = 1 else 1. */
+int msp_model_grad(msp_ctx *ctx, const float *feat_dev, const uint8_t *label_dev, int64_t count,
+                   float pos_weight, float *grad_dev, float *loss, void *stream);
+
+typedef struct {
+    int epochs;        /* passes over the data                               [20] */
+    int batch;         /* rows per optimizer step, a multiple of 64        [8192] */
+    float lr;          /* Adam step size                                   [1e-3] */
+    float pos_weight;  /* weight of label-1 rows; <= 0: negatives/positives  [0] */
+    uint64_t seed;     /* epoch shuffles                                      [1] */
+    int use_graph;     /* 1: replay each epoch's launches as one HIP graph    [1] */
+} msp_train_params;
+int msp_train_params_default(msp_train_params *tp);
+
+/* Train the model by Adam (beta 0.9/0.999, eps 1e-8; fresh optimizer state
+ * each call) on the mean weighted logistic loss of shuffled mini-batches.
+ * loss_per_epoch (host, epochs floats, may be NULL) receives each epoch's
+ * mean batch loss. */
+int msp_model_train(msp_ctx *ctx, const float *feat_dev, const uint8_t *label_dev, int64_t count,
+                    const msp_train_params *tp, float *loss_per_epoch, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *msp_strerror(int code);

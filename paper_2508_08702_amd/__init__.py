@@ -33,12 +33,17 @@ MSP_ALL = 0
 MSP_FIRST = 1
 MSP_PLAIN = 0
 MSP_LEARNED = 1
+MSP_DISCREPANCY = 2
 MSP_MAX_N = 127
+MSP_NFEAT = 16
+MSP_MODEL_NPARAM = 5313
 
 # every symbol include/msp.h declares
 EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_strerror",
+    "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
+    "msp_model_grad", "msp_train_params_default", "msp_model_train",
 )
 
 
@@ -75,6 +80,11 @@ class BatchDesc(C.Structure):
                 ("x_off", C.c_int64), ("cap", C.c_int64)]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("pos_weight", C.c_float),
+                ("seed", C.c_uint64), ("use_graph", C.c_int)]
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_08702_amd.build`")
@@ -96,6 +106,23 @@ def _load() -> C.CDLL:
     lib.msp_solve_batch.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params), vp,
                                     C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(Stats), vp]
     lib.msp_solve_batch.restype = i32
+    lib.msp_root_trace.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.POINTER(Params), vp, vp, i64,
+                                   C.POINTER(i64), C.POINTER(i64), C.POINTER(Stats), vp]
+    lib.msp_root_trace.restype = i32
+    lib.msp_model_init.argtypes = [vp, C.c_uint64]
+    lib.msp_model_init.restype = i32
+    lib.msp_model_set.argtypes = [vp, vp]
+    lib.msp_model_set.restype = i32
+    lib.msp_model_get.argtypes = [vp, vp]
+    lib.msp_model_get.restype = i32
+    lib.msp_model_score.argtypes = [vp, vp, i64, vp, vp]
+    lib.msp_model_score.restype = i32
+    lib.msp_model_grad.argtypes = [vp, vp, vp, i64, C.c_float, vp, C.POINTER(C.c_float), vp]
+    lib.msp_model_grad.restype = i32
+    lib.msp_train_params_default.argtypes = [C.POINTER(TrainParams)]
+    lib.msp_train_params_default.restype = i32
+    lib.msp_model_train.argtypes = [vp, vp, vp, i64, C.POINTER(TrainParams), vp, vp]
+    lib.msp_model_train.restype = i32
     lib.msp_strerror.argtypes = [i32]
     lib.msp_strerror.restype = C.c_char_p
     return lib
@@ -302,3 +329,113 @@ def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, or
         rows = min(nf[i], cap)
         xs.append(x_all[desc[i].x_off: desc[i].x_off + cap * n].view(cap, n)[:rows])
     return BatchResult(x=xs, n_found=list(nf), status=list(st), stats=[s.as_dict() for s in stats], rc=rc)
+
+
+# ---- root traces and the root-scoring model ---------------------------------
+
+@dataclass
+class Trace:
+    feat: torch.Tensor    # float32 (roots, MSP_NFEAT) on the device
+    label: torch.Tensor   # uint8 (roots,) on the device: 1 iff a solution lies below the root
+    n_found: int
+    stats: dict
+
+
+def msp_root_trace(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.Tensor, *,
+                   params: Params | None = None, cap_roots: int = 1 << 20) -> Trace:
+    """Exhaustive enumeration that also returns per-root features and labels."""
+    m, n = A.shape
+    k = basis.shape[0]
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    bp = _dev_ptr(basis, torch.int64, dev, "basis")
+    p = params if params is not None else msp_params_default()
+    for _ in range(2):
+        feat = torch.empty((max(cap_roots, 1), MSP_NFEAT), dtype=torch.float32, device=dev)
+        label = torch.empty((max(cap_roots, 1),), dtype=torch.uint8, device=dev)
+        nr, nf, st = C.c_int64(0), C.c_int64(0), Stats()
+        rc = lib().msp_root_trace(ctx.handle, m, n, ap, dp, bp, k, C.byref(p), feat.data_ptr(), label.data_ptr(),
+                                  int(cap_roots), C.byref(nr), C.byref(nf), C.byref(st), _stream_handle(dev))
+        if rc == MSP_E_CAPACITY and nr.value > cap_roots:
+            cap_roots = nr.value  # more roots than room: run again with room for all
+            continue
+        if rc != MSP_OK:
+            raise MspError(rc, "msp_root_trace")
+        return Trace(feat=feat[: nr.value], label=label[: nr.value], n_found=nf.value, stats=st.as_dict())
+    raise MspError(MSP_E_CAPACITY, "msp_root_trace")
+
+
+def msp_model_init(ctx: Context, seed: int = 0) -> None:
+    rc = lib().msp_model_init(ctx.handle, int(seed))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_init")
+
+
+def msp_model_set(ctx: Context, w) -> None:
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    if w.size != MSP_MODEL_NPARAM:
+        raise ValueError(f"expected {MSP_MODEL_NPARAM} parameters, got {w.size}")
+    rc = lib().msp_model_set(ctx.handle, w.ctypes.data)
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_set")
+
+
+def msp_model_get(ctx: Context):
+    import numpy as np
+    w = np.empty(MSP_MODEL_NPARAM, dtype=np.float32)
+    rc = lib().msp_model_get(ctx.handle, w.ctypes.data)
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_get")
+    return w
+
+
+def msp_model_score(ctx: Context, feat: torch.Tensor) -> torch.Tensor:
+    dev = ctx.device
+    fp = _dev_ptr(feat, torch.float32, dev, "feat")
+    count = feat.shape[0]
+    logit = torch.empty((count,), dtype=torch.float32, device=dev)
+    rc = lib().msp_model_score(ctx.handle, fp, count, logit.data_ptr(), _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_score")
+    return logit
+
+
+def msp_model_grad(ctx: Context, feat: torch.Tensor, label: torch.Tensor, pos_weight: float = 1.0):
+    """Returns (gradient as a float32 device tensor, loss)."""
+    dev = ctx.device
+    fp = _dev_ptr(feat, torch.float32, dev, "feat")
+    lp = _dev_ptr(label, torch.uint8, dev, "label")
+    grad = torch.empty((MSP_MODEL_NPARAM,), dtype=torch.float32, device=dev)
+    loss = C.c_float(0.0)
+    rc = lib().msp_model_grad(ctx.handle, fp, lp, feat.shape[0], float(pos_weight), grad.data_ptr(),
+                              C.byref(loss), _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_grad")
+    return grad, loss.value
+
+
+def msp_train_params_default(**overrides) -> TrainParams:
+    tp = TrainParams()
+    rc = lib().msp_train_params_default(C.byref(tp))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_train_params_default")
+    for key, val in overrides.items():
+        if not hasattr(tp, key):
+            raise KeyError(key)
+        setattr(tp, key, val)
+    return tp
+
+
+def msp_model_train(ctx: Context, feat: torch.Tensor, label: torch.Tensor, tp: TrainParams | None = None):
+    """Train the context's model on (feat, label); returns the per-epoch losses."""
+    dev = ctx.device
+    fp = _dev_ptr(feat, torch.float32, dev, "feat")
+    lp = _dev_ptr(label, torch.uint8, dev, "label")
+    tp = tp if tp is not None else msp_train_params_default()
+    losses = (C.c_float * max(1, tp.epochs))()
+    rc = lib().msp_model_train(ctx.handle, fp, lp, feat.shape[0], C.byref(tp), losses, _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_model_train")
+    return list(losses)[: tp.epochs]

@@ -1,7 +1,7 @@
 // C ABI of libmsp (declared in include/msp.h): argument checks, the
 // context's device workspace, and the sequence of kernel launches for each
 // call.  No arithmetic of the method happens on the host: every step runs in
-// the kernels of gs.hip, rootgen.hip, walk.hip and lll.hip.
+// the kernels of gs.hip, rootgen.hip, walk.hip, lll.hip and order.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <random>
 #include <vector>
 
 #include "../../include/msp.h"
@@ -103,6 +104,18 @@ struct msp_ctx {
     Buf pool_u, pool_meta, pool_ready;
     long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
+    // root orders
+    Buf feat, key, key_out, idx_in, sort_tmp;
+    // roots of the last enumeration (for tracing)
+    int last_cur = 0, last_L = 0, last_k = 0, last_dim = 0, last_ws = 0, last_m = 0;
+    int64_t last_np = 0;
+    double last_R = 0.0;
+    Buf sol_u, trace_x;
+    // root-scoring model
+    bool has_model = false;
+    Buf w_master, w_q, adam_m, adam_v, step, partial, loss_acc, dev_loss, npos;
+    Buf sh_keys, sh_keys_out, sh_idx, sh_perm, sh_tmp;
+    hipStream_t aux = nullptr;
 };
 
 namespace {
@@ -225,6 +238,11 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->pool_u.release();
     c->pool_meta.release();
     c->pool_ready.release();
+    for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->sol_u, &c->trace_x, &c->w_master,
+                   &c->w_q, &c->adam_m, &c->adam_v, &c->step, &c->partial, &c->loss_acc, &c->dev_loss, &c->npos,
+                   &c->sh_keys, &c->sh_keys_out, &c->sh_idx, &c->sh_perm, &c->sh_tmp})
+        b->release();
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;
@@ -250,12 +268,13 @@ int msp_gram_schmidt(msp_ctx *c, int k, int dim, const int64_t *basis_dev, doubl
 
 static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
                           const int64_t *basis_dev, int k, int mode, int order, const msp_params *pin, uint8_t *x_dev,
-                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream) {
+                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream, int8_t *sol_u = nullptr) {
     auto t_call = std::chrono::steady_clock::now();
     if (!c || !A_dev || !d_dev || !basis_dev || !n_found || (cap > 0 && !x_dev) || cap < 0) return MSP_E_ARG;
     if (m < 1 || n < 1 || m > n || n > MSP_MAX_N || k != n - m + 1) return MSP_E_ARG;
     if (mode != MSP_ALL && mode != MSP_FIRST) return MSP_E_ARG;
-    if (order != MSP_PLAIN) return MSP_E_UNSUPPORTED;
+    if (order != MSP_PLAIN && order != MSP_LEARNED && order != MSP_DISCREPANCY) return MSP_E_ARG;
+    if (order == MSP_LEARNED && !c->has_model) return MSP_E_ARG;
     msp_params p;
     msp_params_default(&p);
     if (pin) p = *pin;
@@ -362,6 +381,39 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     MSP_TRY(c->pool_meta.ensure((size_t)pcap * sizeof(int4)));
     MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));
     Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), pcap};
+    c->last_cur = cur;
+    c->last_np = np;
+    c->last_L = L;
+    c->last_k = k;
+    c->last_dim = dim;
+    c->last_ws = ws;
+    c->last_m = m;
+    c->last_R = R;
+    // ---- root order for first-solution search ----
+    const bool ordered = order != MSP_PLAIN && np > 1;
+    if (ordered) {
+        MSP_TRY(hipEventRecord(c->ev[6], st));
+        MSP_TRY(c->feat.ensure((size_t)np * kNumFeat * sizeof(float)));
+        MSP_TRY(c->key.ensure((size_t)np * sizeof(float)));
+        MSP_TRY(c->key_out.ensure((size_t)np * sizeof(float)));
+        MSP_TRY(c->idx_in.ensure((size_t)np * sizeof(int64_t)));
+        MSP_TRY(c->order.ensure((size_t)np * sizeof(int64_t)));
+        FeatArgs fa{k, dim, m, L, ws, c->fr[cur].view(), np, c->gs_mu.as<double>(), c->gs_beta.as<double>(), R,
+                    c->feat.as<float>()};
+        MSP_TRY(launch_root_features(fa, st));
+        if (order == MSP_LEARNED)
+            MSP_TRY(launch_mlp_score(c->w_q.as<float>(), c->feat.as<float>(), np, c->key.as<float>(), st));
+        else
+            MSP_TRY(launch_disc_keys(c->feat.as<float>(), np, k - L, c->key.as<float>(), st));
+        size_t tb = 0;
+        MSP_TRY(sort_scores_desc(nullptr, &tb, c->key.as<float>(), c->key_out.as<float>(), c->idx_in.as<int64_t>(),
+                                 c->order.as<int64_t>(), np, st));
+        MSP_TRY(c->sort_tmp.ensure(tb));
+        tb = c->sort_tmp.cap;
+        MSP_TRY(sort_scores_desc(c->sort_tmp.p, &tb, c->key.as<float>(), c->key_out.as<float>(),
+                                 c->idx_in.as<int64_t>(), c->order.as<int64_t>(), np, st));
+        MSP_TRY(hipEventRecord(c->ev[7], st));
+    }
     if (np > 0) {
         MSP_TRY(launch_pool_init(c->fr[cur].view(), np, k, L, pool, st));
         const unsigned long long qt = (unsigned long long)np;
@@ -386,7 +438,8 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.nroots = np;
         wa.root_w = c->fr[cur].w.as<double>();
         wa.root_l = c->fr[cur].l.as<double>();
-        wa.order = nullptr;
+        wa.order = ordered ? c->order.as<int64_t>() : nullptr;
+        wa.sol_u = sol_u;
         wa.head = &ctl->qhead;
         wa.tail = &ctl->qtail;
         wa.pending = &ctl->pending;
@@ -430,7 +483,9 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         stats->gs_ms = elapsed(c->ev[0], c->ev[1]);
         stats->rootgen_ms = elapsed(c->ev[2], c->ev[3]);
         stats->kernel_ms = elapsed(c->ev[4], c->ev[5]);
-        stats->ttfs_ms = (h.t_first && h.t_start) ? (double)(h.t_first - h.t_start) / c->wall_khz : -1.0;
+        stats->ordering_ms = ordered ? elapsed(c->ev[6], c->ev[7]) : 0.0;
+        stats->ttfs_ms =
+            (h.t_first && h.t_start) ? (double)(h.t_first - h.t_start) / c->wall_khz + stats->ordering_ms : -1.0;
         stats->total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
     }
@@ -577,6 +632,231 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
         if (s != MSP_OK && first_bad == MSP_OK) first_bad = s;
     }
     return first_bad;
+}
+
+
+// ---------------------------------------------------------------------------
+// Root traces and the root-scoring model.
+
+int msp_root_trace(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
+                   int k, const msp_params *p, float *feat_dev, uint8_t *label_dev, int64_t cap_roots,
+                   int64_t *nroots, int64_t *n_found, msp_stats *stats, void *stream) {
+    if (!c || !nroots || !n_found || cap_roots < 0 || (cap_roots > 0 && (!feat_dev || !label_dev))) return MSP_E_ARG;
+    *nroots = 0;
+    *n_found = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t scap = kTraceSolutions;
+    if (n < 1 || k < 1) return MSP_E_ARG;
+    MSP_TRY(c->trace_x.ensure((size_t)scap * n));
+    MSP_TRY(c->sol_u.ensure((size_t)scap * k));
+    int rc = enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, MSP_ALL, MSP_PLAIN, p, c->trace_x.as<uint8_t>(), scap,
+                            n_found, stats, stream, c->sol_u.as<int8_t>());
+    if (rc != MSP_OK) return rc;
+    const int64_t np = c->last_np;
+    *nroots = np;
+    if (np > cap_roots) return MSP_E_CAPACITY;
+    if (np == 0) return MSP_OK;
+    FeatArgs fa{c->last_k, c->last_dim, c->last_m, c->last_L, c->last_ws, c->fr[c->last_cur].view(), np,
+                c->gs_mu.as<double>(), c->gs_beta.as<double>(), c->last_R, feat_dev};
+    MSP_TRY(launch_root_features(fa, st));
+    MSP_TRY(launch_root_labels(c->fr[c->last_cur].view(), np, c->last_k, c->last_L, c->sol_u.as<int8_t>(),
+                               std::min<int64_t>(*n_found, scap), label_dev, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    return MSP_OK;
+}
+
+namespace {
+int model_alloc(msp_ctx *c) {
+    const size_t nb = (size_t)kNumParams * sizeof(float);
+    MSP_TRY(c->w_master.ensure(nb));
+    MSP_TRY(c->w_q.ensure(nb));
+    MSP_TRY(c->adam_m.ensure(nb));
+    MSP_TRY(c->adam_v.ensure(nb));
+    MSP_TRY(c->step.ensure(sizeof(unsigned long long)));
+    MSP_TRY(c->dev_loss.ensure(sizeof(float)));
+    MSP_TRY(c->npos.ensure(sizeof(unsigned long long)));
+    if (!c->aux) MSP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    return MSP_OK;
+}
+
+int model_upload(msp_ctx *c, const float *w) {
+    int rc = model_alloc(c);
+    if (rc != MSP_OK) return rc;
+    hipStream_t st = c->aux;
+    MSP_TRY(hipMemcpyAsync(c->w_master.p, w, (size_t)kNumParams * sizeof(float), hipMemcpyHostToDevice, st));
+    MSP_TRY(launch_bf16_round(c->w_master.as<float>(), c->w_q.as<float>(), st));
+    MSP_TRY(hipStreamSynchronize(st));
+    c->has_model = true;
+    return MSP_OK;
+}
+}  // namespace
+
+int msp_model_init(msp_ctx *c, uint64_t seed) {
+    if (!c) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    // He-normal weights for the ReLU layers, N(0, 1/64) for the output
+    // layer, zero biases.
+    std::vector<float> w(kNumParams, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> n1(0.0f, std::sqrt(2.0f / kNumFeat)), n2(0.0f, std::sqrt(2.0f / kHidden)),
+        n3(0.0f, std::sqrt(1.0f / kHidden));
+    size_t o = 0;
+    for (int i = 0; i < kHidden * kNumFeat; ++i) w[o++] = n1(rng);
+    o += kHidden;
+    for (int i = 0; i < kHidden * kHidden; ++i) w[o++] = n2(rng);
+    o += kHidden;
+    for (int i = 0; i < kHidden; ++i) w[o++] = n3(rng);
+    return model_upload(c, w.data());
+}
+
+int msp_model_set(msp_ctx *c, const float *w) {
+    if (!c || !w) return MSP_E_ARG;
+    for (int i = 0; i < kNumParams; ++i)
+        if (!std::isfinite(w[i])) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    return model_upload(c, w);
+}
+
+int msp_model_get(msp_ctx *c, float *w) {
+    if (!c || !w || !c->has_model) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    MSP_TRY(hipMemcpyAsync(w, c->w_master.p, (size_t)kNumParams * sizeof(float), hipMemcpyDeviceToHost, c->aux));
+    MSP_TRY(hipStreamSynchronize(c->aux));
+    return MSP_OK;
+}
+
+int msp_model_score(msp_ctx *c, const float *feat_dev, int64_t count, float *logit_dev, void *stream) {
+    if (!c || count < 0 || (count > 0 && (!feat_dev || !logit_dev)) || !c->has_model) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    MSP_TRY(launch_mlp_score(c->w_q.as<float>(), feat_dev, count, logit_dev, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    return MSP_OK;
+}
+
+int msp_model_grad(msp_ctx *c, const float *feat_dev, const uint8_t *label_dev, int64_t count, float pos_weight,
+                   float *grad_dev, float *loss, void *stream) {
+    if (!c || count < 1 || !feat_dev || !label_dev || !grad_dev || !loss || !c->has_model) return MSP_E_ARG;
+    if (!(pos_weight > 0.0f) || count > (int64_t)INT32_MAX) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t waves = (count + 63) / 64;
+    if (waves > (int64_t)INT32_MAX) return MSP_E_ARG;
+    MSP_TRY(c->partial.ensure((size_t)waves * kPartialStride * sizeof(float)));
+    MlpGradArgs ga{c->w_q.as<float>(), feat_dev, label_dev, nullptr, count, count, nullptr, 1, pos_weight,
+                   c->partial.as<float>()};
+    MSP_TRY(launch_mlp_grad(ga, (int)waves, st));
+    MSP_TRY(launch_grad_sum(c->partial.as<float>(), (int)waves, grad_dev, c->dev_loss.as<float>(), st));
+    MSP_TRY(hipMemcpyAsync(loss, c->dev_loss.p, sizeof(float), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    return MSP_OK;
+}
+
+int msp_train_params_default(msp_train_params *tp) {
+    if (!tp) return MSP_E_ARG;
+    tp->epochs = 20;
+    tp->batch = 8192;
+    tp->lr = 1e-3f;
+    tp->pos_weight = 0.0f;
+    tp->seed = 1;
+    tp->use_graph = 1;
+    return MSP_OK;
+}
+
+int msp_model_train(msp_ctx *c, const float *feat_dev, const uint8_t *label_dev, int64_t count,
+                    const msp_train_params *tpin, float *loss_per_epoch, void *stream) {
+    if (!c || count < 1 || !feat_dev || !label_dev || !c->has_model) return MSP_E_ARG;
+    msp_train_params tp;
+    msp_train_params_default(&tp);
+    if (tpin) tp = *tpin;
+    if (tp.epochs < 1 || tp.batch < 64 || tp.batch % 64 != 0 || !(tp.lr > 0.0f) || count > (int64_t)INT32_MAX)
+        return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t caller = (hipStream_t)stream;
+    MSP_TRY(hipStreamSynchronize(caller));  // inputs were produced on the caller's stream
+    hipStream_t st = c->aux;
+    const int64_t B = tp.batch;
+    const int64_t spe = (count + B - 1) / B;
+    const int waves = (int)(B / 64);
+    MSP_TRY(c->partial.ensure((size_t)waves * kPartialStride * sizeof(float)));
+    MSP_TRY(c->loss_acc.ensure((size_t)tp.epochs * sizeof(float)));
+    MSP_TRY(c->sh_keys.ensure((size_t)count * sizeof(uint32_t)));
+    MSP_TRY(c->sh_keys_out.ensure((size_t)count * sizeof(uint32_t)));
+    MSP_TRY(c->sh_idx.ensure((size_t)count * sizeof(int32_t)));
+    MSP_TRY(c->sh_perm.ensure((size_t)count * sizeof(int32_t)));
+    size_t tb = 0;
+    MSP_TRY(shuffle_perm(nullptr, &tb, c->sh_keys.as<uint32_t>(), c->sh_keys_out.as<uint32_t>(),
+                         c->sh_idx.as<int32_t>(), c->sh_perm.as<int32_t>(), count, tp.seed, 0, st));
+    MSP_TRY(c->sh_tmp.ensure(tb));
+    float pw = tp.pos_weight;
+    if (!(pw > 0.0f)) {
+        // balance the classes: weight positives by negatives / positives
+        MSP_TRY(hipMemsetAsync(c->npos.p, 0, sizeof(unsigned long long), st));
+        MSP_TRY(launch_count_pos(label_dev, count, c->npos.as<unsigned long long>(), st));
+        unsigned long long npos = 0;
+        MSP_TRY(hipMemcpyAsync(&npos, c->npos.p, sizeof(npos), hipMemcpyDeviceToHost, st));
+        MSP_TRY(hipStreamSynchronize(st));
+        pw = npos > 0 ? (float)((double)(count - (int64_t)npos) / (double)npos) : 1.0f;
+        if (pw < 1.0f) pw = 1.0f;
+    }
+    // fresh optimizer state
+    MSP_TRY(hipMemsetAsync(c->adam_m.p, 0, (size_t)kNumParams * sizeof(float), st));
+    MSP_TRY(hipMemsetAsync(c->adam_v.p, 0, (size_t)kNumParams * sizeof(float), st));
+    MSP_TRY(hipMemsetAsync(c->step.p, 0, sizeof(unsigned long long), st));
+    MSP_TRY(hipMemsetAsync(c->loss_acc.p, 0, (size_t)tp.epochs * sizeof(float), st));
+    MlpGradArgs ga{c->w_q.as<float>(), feat_dev, label_dev, c->sh_perm.as<int32_t>(), count, B,
+                   c->step.as<unsigned long long>(), spe, pw, c->partial.as<float>()};
+    AdamArgs aa{c->w_master.as<float>(), c->w_q.as<float>(), c->adam_m.as<float>(), c->adam_v.as<float>(),
+                c->partial.as<float>(), waves, c->step.as<unsigned long long>(), spe, tp.lr,
+                c->loss_acc.as<float>()};
+    // One epoch = spe optimizer steps; every kernel reads the step counter
+    // from device memory, so the same launches (or their graph) replay for
+    // every epoch.
+    hipGraphExec_t exec = nullptr;
+    if (tp.use_graph) {
+        hipGraph_t graph = nullptr;
+        MSP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int64_t s = 0; s < spe && e == hipSuccess; ++s) {
+            e = launch_mlp_grad(ga, waves, st);
+            if (e == hipSuccess) e = launch_adam(aa, st);
+        }
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return map_err(e != hipSuccess ? e : e2);
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return map_err(e);
+    }
+    int rc = MSP_OK;
+    for (int ep = 0; ep < tp.epochs && rc == MSP_OK; ++ep) {
+        size_t tbe = c->sh_tmp.cap;
+        hipError_t e = shuffle_perm(c->sh_tmp.p, &tbe, c->sh_keys.as<uint32_t>(), c->sh_keys_out.as<uint32_t>(),
+                                    c->sh_idx.as<int32_t>(), c->sh_perm.as<int32_t>(), count, tp.seed, ep, st);
+        if (e == hipSuccess) {
+            if (exec) {
+                e = hipGraphLaunch(exec, st);
+            } else {
+                for (int64_t s = 0; s < spe && e == hipSuccess; ++s) {
+                    e = launch_mlp_grad(ga, waves, st);
+                    if (e == hipSuccess) e = launch_adam(aa, st);
+                }
+            }
+        }
+        if (e != hipSuccess) rc = map_err(e);
+    }
+    if (rc == MSP_OK && loss_per_epoch) {
+        hipError_t e = hipMemcpyAsync(loss_per_epoch, c->loss_acc.p, (size_t)tp.epochs * sizeof(float),
+                                      hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) rc = map_err(e);
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (rc == MSP_OK && e != hipSuccess) rc = map_err(e);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return rc;
 }
 
 }  // extern "C"

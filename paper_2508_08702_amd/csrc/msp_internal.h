@@ -97,6 +97,7 @@ struct WalkArgs {
     long long *pending;            // items created and not yet finished
     double *stack;                 // per walker k entries x 4 doubles
     uint8_t *x_out;
+    int8_t *sol_u;                 // optional: u_0..u_{k-1} of each written solution (cap x k)
     int64_t cap;
     unsigned long long *n_found;
     unsigned long long *counters;  // [0] evals [1] nodes [2] expansions [3] leaves [4] items done
@@ -118,6 +119,58 @@ int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
 int walk_max_level(int dimp, int k);         // largest split level whose walker fits in LDS
 
 hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
+
+// ---- root orders and the root-scoring MLP (order.hip) ----
+constexpr int kNumFeat = 16;      // features per root
+constexpr int kHidden = 64;       // width of both hidden layers
+constexpr int kNumParams = kHidden * kNumFeat + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
+constexpr int kPartialStride = kNumParams + 7;
+constexpr int64_t kTraceSolutions = 1 << 16;  // solutions recorded by a root trace  // floats per partial-gradient row (params + loss, padded)
+
+struct FeatArgs {
+    int k, dim, m, L, ws;
+    Frontier roots;                // records at level L
+    int64_t np;
+    const double *mu, *beta;       // Gram-Schmidt data (mu k x k row-major)
+    double R;                      // l2 bound n + 1
+    float *feat;                   // np x kNumFeat
+};
+hipError_t launch_root_features(const FeatArgs &a, hipStream_t st);
+hipError_t launch_root_labels(Frontier roots, int64_t np, int k, int L, const int8_t *sol_u, int64_t nsol,
+                              uint8_t *label, hipStream_t st);
+hipError_t launch_disc_keys(const float *feat, int64_t np, int levels, float *key, hipStream_t st);
+hipError_t launch_mlp_score(const float *wq, const float *feat, int64_t count, float *logit, hipStream_t st);
+
+struct MlpGradArgs {
+    const float *wq;               // BF16-rounded weights
+    const float *feat;             // count x kNumFeat
+    const uint8_t *label;          // count
+    const int32_t *perm;           // sample order (nullptr = identity)
+    int64_t count, batch;
+    const unsigned long long *step;  // optimizer step counter (nullptr: the batch starting at 0)
+    int64_t steps_per_epoch;
+    float pos_weight;
+    float *partial;                // waves x kPartialStride
+};
+hipError_t launch_mlp_grad(const MlpGradArgs &a, int waves, hipStream_t st);
+hipError_t launch_grad_sum(const float *partial, int waves, float *grad, float *loss, hipStream_t st);
+
+struct AdamArgs {
+    float *master, *wq, *m, *v;
+    const float *partial;
+    int waves;
+    unsigned long long *step;
+    int64_t steps_per_epoch;
+    float lr;
+    float *loss_acc;               // per epoch
+};
+hipError_t launch_adam(const AdamArgs &a, hipStream_t st);  // Adam, then step += 1
+hipError_t launch_bf16_round(const float *master, float *wq, hipStream_t st);
+hipError_t launch_count_pos(const uint8_t *label, int64_t count, unsigned long long *npos, hipStream_t st);
+hipError_t sort_scores_desc(void *temp, size_t *temp_bytes, const float *key_in, float *key_out, int64_t *idx_in,
+                            int64_t *idx_out, int64_t n, hipStream_t st);
+hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t *keys_out, int32_t *idx,
+                        int32_t *perm, int64_t n, unsigned long long seed, int epoch, hipStream_t st);
 
 // Per-instance fields are read as base[i * stride] (in 4-byte units), so a
 // packed array of descriptor structs serves as the per-instance arrays.

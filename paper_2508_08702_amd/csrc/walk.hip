@@ -252,6 +252,11 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 if (ok) {
                     const unsigned long long slot = atomicAdd(a.n_found, 1ull);
                     if ((int64_t)slot < a.cap) {
+                        if (a.sol_u) {
+                            int8_t *so = a.sol_u + (size_t)slot * k;
+                            so[0] = (int8_t)u;
+                            for (int i = 1; i < k; ++i) so[i] = my_u[k - 1 - i];
+                        }
                         uint8_t *xo = a.x_out + (size_t)slot * a.n;
                         for (int j = 0; j < a.n; ++j) {
                             int64_t sv = (int64_t)u * a.basis[j];
