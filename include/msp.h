@@ -87,7 +87,8 @@ typedef struct {
     double eps;           /* relative slack of both pruning tests            [1e-9] */
     int split_depth;      /* levels enumerated before the subtree split; -1 = auto [-1] */
     int block;            /* walk kernel workgroup size cap (256|512); 0 = auto [0] */
-    int target_roots;     /* root count the automatic split aims for; 0 = auto  [0] */
+    int target_roots;     /* root count the automatic split aims for; 0 = auto:
+                           * 512 per CU for MSP_ALL, 16384 per CU for MSP_FIRST [0] */
     int hoelder;          /* 1: apply the Hoelder test (Thm 2)                  [1] */
     int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
     double time_cap_ms;   /* enumeration wall-time cap; <= 0 = none             [0] */

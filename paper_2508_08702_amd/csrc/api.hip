@@ -310,8 +310,13 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
 
     // ---- root generation: levels k-1 .. L breadth first ----
     const int64_t walkers = (int64_t)c->num_cus * 256;  // lanes of the walk kernel
-    // the walker splits work dynamically, so a few roots per lane suffice
-    const int64_t target = p.target_roots > 0 ? p.target_roots : std::max<int64_t>(2 * walkers, 4096);
+    // The walker splits work dynamically, so for an exhaustive walk a few
+    // roots per lane suffice.  A first-solution search wants small subtrees:
+    // a lane walks its subtree alone until the roots run out, so the root
+    // order only pays off when each subtree is a short walk.
+    const int64_t target = p.target_roots > 0 ? p.target_roots
+                           : mode == MSP_FIRST ? 64 * walkers
+                                               : std::max<int64_t>(2 * walkers, 4096);
     const int64_t fcap = std::max<int64_t>(4 * target, 1 << 16);
     MSP_TRY(c->fr[0].ensure(fcap, k, ws));
     MSP_TRY(c->fr[1].ensure(fcap, k, ws));
