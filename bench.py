@@ -36,6 +36,24 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 
+# HBM bytes per walk-kernel launch measured with rocprofv3 counters
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scale factors from a 1 GiB copy in the
+# same run), valid only for the kernel source they were taken on.
+WALK_TRAFFIC = {
+    "m9-1": {"bytes": 3.479e12,
+             "sha256": "0211b808d9dbf866c941591176b160556ea3ad9763e723ee4f442f1f0897982b",
+             "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
+}
+
+
+def walk_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("walk.hip", "enum_rules.h", "msp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2508_08702_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 WORKLOADS = {
     # name: (description, list of (m, D, seed))
     "m9": ("12 planted instances m=9, n=80, 4 each D=50/100/200 (seeds 4500-4511), exhaustive",
@@ -183,6 +201,8 @@ def main():
         flops += st["nodes"] * (3 * dim + 4) + (st["evals"] - st["nodes"]) * 4
         kern_s += st["kernel_ms"] * 1e-3
     achieved = flops / kern_s / 1e12 if kern_s > 0 else 0.0
+    tr = WALK_TRAFFIC.get(args.workload)
+    traffic = tr["bytes"] if tr and tr["sha256"] == walk_source_hash() else None
     res = {
         "metric": "enum nodes/s + time-to-first-solution, m=9..11, plain vs learned order",
         "value": nodes / wall,
@@ -199,7 +219,8 @@ def main():
         "config": {"workload": desc, "instances": len(insts), "mode": "all", "order": "plain",
                    "nodes_per_step": nodes // max(1, args.steps)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                      "kernel": "walk_kernel", "walk_ms_total": kern_s * 1e3,
                      "walk_launches": len(rec), "walk_ms_avg": kern_s * 1e3 / max(1, len(rec)),
                      "flops_per_node": "3*(n+1)+4, plus 4 per failed candidate"},
