@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--ttfs", default="m9", choices=("none", "m9", "m11"),
                     help="first-solution set timed per order (none to skip)")
     ap.add_argument("--ttfs-cap-ms", type=float, default=10000.0)
+    ap.add_argument("--ttfs-seeds", default="", help="comma-separated subset of the TTFS set's seeds")
     ap.add_argument("--orders", default="plain,learned", help="orders timed on the TTFS set")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2508_08702_amd", "order_model.npy"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,6 +92,9 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
     """First-solution search per instance and order; end-to-end times
     include msp_reduce, root generation, root ordering and the walk."""
     insts = mi.m9_eval() if args.ttfs == "m9" else mi.m11_eval()
+    if args.ttfs_seeds:
+        keep = {int(x) for x in args.ttfs_seeds.split(",")}
+        insts = [i for i in insts if i.seed in keep]
     orders = {"plain": M.MSP_PLAIN, "learned": M.MSP_LEARNED, "discrepancy": M.MSP_DISCREPANCY}
     names = [o for o in args.orders.split(",") if o]
     if "learned" in names:
@@ -117,7 +121,8 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
             row[name] = {"ttfs_ms": st["ttfs_ms"] if ok else None, "end_to_end_ms": e2e if ok else None,
                          "censored": not ok, "status": r.status, "roots": st["roots"],
                          "split_depth": st["split_depth"], "ordering_ms": st["ordering_ms"],
-                         "rootgen_ms": st["rootgen_ms"]}
+                         "rootgen_ms": st["rootgen_ms"], "stages": st["stages"], "root_level": st["root_level"],
+                         "initial_items": st["initial_items"]}
         print(json.dumps({"ttfs_instance": row}), file=sys.stderr, flush=True)
         per.append(row)
 

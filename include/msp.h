@@ -92,6 +92,10 @@ typedef struct {
     int hoelder;          /* 1: apply the Hoelder test (Thm 2)                  [1] */
     int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
     double time_cap_ms;   /* enumeration wall-time cap; <= 0 = none             [0] */
+    int refine;           /* MSP_FIRST with a non-plain order: refinement stages
+                           * (see msp_enumerate); -1 = auto (up to 64), 0 = off [-1] */
+    int refine_keep;      /* best nodes expanded further per stage; 0 = auto
+                           * (256 per CU)                                        [0] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).
@@ -114,6 +118,9 @@ typedef struct {
     double ttfs_ms;          /* MSP_FIRST: ordering_ms + walk-kernel start to the
                               * first verified hit (device clock); -1 if none   */
     double total_ms;         /* whole call                                       */
+    int32_t stages;          /* refinement stages run (0 without refinement)     */
+    int32_t root_level;      /* level of the walked roots (deepest stage)        */
+    int64_t initial_items;   /* work items before the walk: roots + leftovers    */
 } msp_stats;
 
 /* Fill `p` with the defaults.  Returns MSP_OK or MSP_E_ARG (p == NULL). */
@@ -152,7 +159,13 @@ int msp_gram_schmidt(msp_ctx *ctx, int k, int dim, const int64_t *basis_dev,
  * mode MSP_ALL returns every solution exactly once (unspecified order);
  * MSP_FIRST stops at the first verified solution (one or a few rows).
  * order: MSP_PLAIN, MSP_LEARNED (needs a model: MSP_E_ARG otherwise) or
- * MSP_DISCREPANCY; see above.
+ * MSP_DISCREPANCY; see above.  With MSP_FIRST and a non-plain order the roots
+ * are refined best first: the frontier is ordered, its best p->refine_keep
+ * nodes are expanded a few more levels (in depth-first order) and ordered
+ * again, stage after stage, until the frontier is deep; the walk then takes
+ * the last frontier in order, followed by every stage's remaining nodes
+ * (latest stage first, each in order).  The subtrees still cover the whole
+ * tree once, so the result is as exhaustive as the plain walk.
  * x_dev: uint8 cap x n, rows of 0/1.  *n_found: solutions found (may exceed
  * cap: then only cap rows are written and MSP_E_CAPACITY is returned after the
  * full enumeration).  stats may be NULL.

@@ -58,6 +58,7 @@ class Params(C.Structure):
         ("N", C.c_int64), ("delta", C.c_double), ("eps", C.c_double),
         ("split_depth", C.c_int), ("block", C.c_int), ("target_roots", C.c_int),
         ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
+        ("refine", C.c_int), ("refine_keep", C.c_int),
     ]
 
 
@@ -68,7 +69,8 @@ class Stats(C.Structure):
         ("block", C.c_int32), ("pad", C.c_int32),
         ("reduce_ms", C.c_double), ("gs_ms", C.c_double), ("rootgen_ms", C.c_double),
         ("ordering_ms", C.c_double), ("kernel_ms", C.c_double), ("ttfs_ms", C.c_double),
-        ("total_ms", C.c_double),
+        ("total_ms", C.c_double), ("stages", C.c_int32), ("root_level", C.c_int32),
+        ("initial_items", C.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -39,6 +39,26 @@ struct Buf {
         cap = nb;
         return hipSuccess;
     }
+    // like ensure(), but keeps the first `cap` bytes (copied on the stream)
+    hipError_t grow(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return hipSuccess;
+        size_t nb = std::max<size_t>(bytes, 2 * cap);
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, nb);
+        if (e != hipSuccess) return e;
+        if (p) {
+            e = hipMemcpyAsync(q, p, cap, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                (void)hipFree(q);
+                return e;
+            }
+            (void)hipFree(p);
+        }
+        p = q;
+        cap = nb;
+        return hipSuccess;
+    }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -94,7 +114,7 @@ struct msp_ctx {
     int num_cus = 0;
     double wall_khz = 100000.0;
     Buf gs_bhat, gs_mu, gs_beta;
-    FrontierBuf fr[2];
+    FrontierBuf fr[3];
     Buf counts, offs;
     Buf stack;
     Buf ctl;
@@ -106,6 +126,7 @@ struct msp_ctx {
     hipEvent_t ev[8] = {};
     // root orders
     Buf feat, key, key_out, idx_in, sort_tmp;
+    Buf left_u, left_meta, top_idx;  // refinement: stage leftovers, best-node indices
     // roots of the last enumeration (for tracing)
     int last_cur = 0, last_L = 0, last_k = 0, last_dim = 0, last_ws = 0, last_m = 0;
     int64_t last_np = 0;
@@ -164,6 +185,8 @@ int msp_params_default(msp_params *p) {
     p->hoelder = 1;
     p->onedir = 1;
     p->time_cap_ms = 0.0;
+    p->refine = -1;
+    p->refine_keep = 0;
     return MSP_OK;
 }
 
@@ -224,6 +247,10 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->gs_beta.release();
     c->fr[0].release();
     c->fr[1].release();
+    c->fr[2].release();
+    c->left_u.release();
+    c->left_meta.release();
+    c->top_idx.release();
     c->counts.release();
     c->offs.release();
     c->stack.release();
@@ -279,6 +306,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     msp_params_default(&p);
     if (pin) p = *pin;
     if (!(p.eps >= 0.0) || p.split_depth < -1 || p.split_depth > k - 1) return MSP_E_ARG;
+    if (p.refine < -1 || p.refine_keep < 0 || p.target_roots < 0) return MSP_E_ARG;
     *n_found = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -310,66 +338,173 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
 
     // ---- root generation: levels k-1 .. L breadth first ----
     const int64_t walkers = (int64_t)c->num_cus * 256;  // lanes of the walk kernel
+    const bool ordered_first = mode == MSP_FIRST && order != MSP_PLAIN;
+    const bool refine = ordered_first && p.refine != 0;
+    const int max_stages = p.refine > 0 ? p.refine : 64;
+    const int64_t keep = p.refine_keep > 0 ? p.refine_keep : walkers;
     // The walker splits work dynamically, so for an exhaustive walk a few
     // roots per lane suffice.  A first-solution search wants small subtrees:
     // a lane walks its subtree alone until the roots run out, so the root
-    // order only pays off when each subtree is a short walk.
+    // order only pays off when each subtree is a short walk (refinement gets
+    // there in stages, from a smaller first frontier).
     const int64_t target = p.target_roots > 0 ? p.target_roots
-                           : mode == MSP_FIRST ? 64 * walkers
-                                               : std::max<int64_t>(2 * walkers, 4096);
-    const int64_t fcap = std::max<int64_t>(4 * target, 1 << 16);
+                           : refine             ? 16 * walkers
+                           : mode == MSP_FIRST  ? 64 * walkers
+                                                : std::max<int64_t>(2 * walkers, 4096);
+    const int64_t fcap = std::max<int64_t>(4 * std::max<int64_t>(target, keep), 1 << 16);
     MSP_TRY(c->fr[0].ensure(fcap, k, ws));
     MSP_TRY(c->fr[1].ensure(fcap, k, ws));
+    if (refine) MSP_TRY(c->fr[2].ensure(fcap, k, ws));
     MSP_TRY(c->counts.ensure((size_t)fcap * sizeof(int64_t)));
     MSP_TRY(c->offs.ensure((size_t)fcap * sizeof(int64_t)));
     MSP_TRY(hipEventRecord(c->ev[2], st));
     MSP_TRY(launch_frontier_init(c->fr[0].view(), k, ws, st));
-    int cur = 0;
-    int64_t np = 1;
-    int L = k;
-    const bool fixed = p.split_depth >= 0;
     // the walker keeps rows b_hat_0 .. b_hat_{L-1} in LDS: split at least this deep
     const int L_fit = walk_max_level(dimp, k);
     if (L_fit < 1) return MSP_E_UNSUPPORTED;
-    for (int t = k - 1; t >= 1; --t) {
-        if (fixed && k - L >= p.split_depth) break;
-        if (!fixed && np >= target && L <= L_fit) break;
-        ExpandArgs ea{};
-        ea.k = k;
-        ea.dim = dim;
-        ea.dimp = dimp;
-        ea.ws = ws;
-        ea.t = t;
-        ea.bhat = c->gs_bhat.as<double>();
-        ea.mu = c->gs_mu.as<double>();
-        ea.beta = c->gs_beta.as<double>();
-        ea.par = c->fr[cur].view();
-        ea.np = np;
-        ea.ch = c->fr[cur ^ 1].view();
-        ea.offs = c->offs.as<int64_t>();
-        ea.counts = c->counts.as<int64_t>();
-        ea.bound = bound;
-        ea.hfac = hfac;
-        ea.hoelder = p.hoelder;
-        ea.onedir = p.onedir;
-        ea.counters = ctl->counters;
-        ea.flags = ctl->flags;
-        MSP_TRY(launch_expand_count(ea, st));
-        MSP_TRY(launch_scan(c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total, st));
-        int64_t total = 0;
-        MSP_TRY(hipMemcpyAsync(&total, &ctl->total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        MSP_TRY(hipStreamSynchronize(st));
-        if (total > fcap) break;  // cannot hold this level: split above it
-        MSP_TRY(launch_expand_write(ea, st));
-        cur ^= 1;
-        np = total;
-        L = t;
-        if (np == 0) break;
-    }
-    MSP_TRY(hipEventRecord(c->ev[3], st));
 
-    // ---- subtree walk (levels L-1 .. 0) ----
-    int wblock = walk_block_for(dimp, k, L);
+    // Expand the frontier in fr[cur] (np nodes of level L) one level at a
+    // time into fr[other], swapping, until done(np, L) or level 1.  A level
+    // that would not fit the frontier buffers is not taken.
+    auto expand = [&](int &cur, int other, int64_t &np, int &L, auto done) -> int {
+        for (int t = L - 1; t >= 1; --t) {
+            if (done(np, L)) break;
+            ExpandArgs ea{};
+            ea.k = k;
+            ea.dim = dim;
+            ea.dimp = dimp;
+            ea.ws = ws;
+            ea.t = t;
+            ea.bhat = c->gs_bhat.as<double>();
+            ea.mu = c->gs_mu.as<double>();
+            ea.beta = c->gs_beta.as<double>();
+            ea.par = c->fr[cur].view();
+            ea.np = np;
+            ea.ch = c->fr[other].view();
+            ea.offs = c->offs.as<int64_t>();
+            ea.counts = c->counts.as<int64_t>();
+            ea.bound = bound;
+            ea.hfac = hfac;
+            ea.hoelder = p.hoelder;
+            ea.onedir = p.onedir;
+            ea.counters = ctl->counters;
+            ea.flags = ctl->flags;
+            MSP_TRY(launch_expand_count(ea, st));
+            MSP_TRY(launch_scan(c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total, st));
+            int64_t total = 0;
+            MSP_TRY(hipMemcpyAsync(&total, &ctl->total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MSP_TRY(hipStreamSynchronize(st));
+            if (total > fcap) break;  // cannot hold this level: split above it
+            MSP_TRY(launch_expand_write(ea, st));
+            std::swap(cur, other);
+            np = total;
+            L = t;
+            if (np == 0) break;
+        }
+        return MSP_OK;
+    };
+
+    int cur = 0;
+    int64_t np = 1;
+    int L = k;
+    {
+        const bool fixed = p.split_depth >= 0;
+        int rc = expand(cur, 1, np, L, [&](int64_t n_, int L_) {
+            return fixed ? k - L_ >= p.split_depth : (n_ >= target && L_ <= L_fit);
+        });
+        if (rc != MSP_OK) return rc;
+    }
+    const int L0 = L;  // highest level of any walked item: the walker's LDS rows
+    const int64_t np0 = np;
+    MSP_TRY(hipEventRecord(c->ev[3], st));
+    c->last_cur = cur;
+    c->last_np = np;
+    c->last_L = L;
+    c->last_k = k;
+    c->last_dim = dim;
+    c->last_ws = ws;
+    c->last_m = m;
+    c->last_R = R;
+
+    // ---- root order for first-solution search ----
+    // Order the np records of frontier fr[f] (level Lf) best first into c->order.
+    auto order_frontier = [&](int f, int64_t nrec, int Lf) -> int {
+        MSP_TRY(c->feat.ensure((size_t)nrec * kNumFeat * sizeof(float)));
+        MSP_TRY(c->key.ensure((size_t)nrec * sizeof(float)));
+        MSP_TRY(c->key_out.ensure((size_t)nrec * sizeof(float)));
+        MSP_TRY(c->idx_in.ensure((size_t)nrec * sizeof(int64_t)));
+        MSP_TRY(c->order.ensure((size_t)nrec * sizeof(int64_t)));
+        FeatArgs fa{k, dim, m, Lf, ws, c->fr[f].view(), nrec, c->gs_mu.as<double>(), c->gs_beta.as<double>(), R,
+                    c->feat.as<float>()};
+        MSP_TRY(launch_root_features(fa, st));
+        if (order == MSP_LEARNED)
+            MSP_TRY(launch_mlp_score(c->w_q.as<float>(), c->feat.as<float>(), nrec, c->key.as<float>(), st));
+        else
+            MSP_TRY(launch_disc_keys(c->feat.as<float>(), nrec, k - Lf, c->key.as<float>(), st));
+        size_t tb = 0;
+        MSP_TRY(sort_scores_desc(nullptr, &tb, c->key.as<float>(), c->key_out.as<float>(), c->idx_in.as<int64_t>(),
+                                 c->order.as<int64_t>(), nrec, st));
+        MSP_TRY(c->sort_tmp.ensure(tb));
+        tb = c->sort_tmp.cap;
+        MSP_TRY(sort_scores_desc(c->sort_tmp.p, &tb, c->key.as<float>(), c->key_out.as<float>(),
+                                 c->idx_in.as<int64_t>(), c->order.as<int64_t>(), nrec, st));
+        return MSP_OK;
+    };
+    const bool ordered = order != MSP_PLAIN && np > 1;
+    int stages = 0;
+    std::vector<std::pair<int64_t, int64_t>> left;  // (offset, count) of each stage's leftovers
+    int64_t nleft = 0;
+    if (ordered) {
+        MSP_TRY(hipEventRecord(c->ev[6], st));
+        int rc = order_frontier(cur, np, L);
+        if (rc != MSP_OK) return rc;
+        if (refine) {
+            // refine until the walked subtrees are a few levels deep
+            const int L_stop = std::max(2, k / 16);
+            while (stages < max_stages && L > L_stop && np > keep) {
+                // the rest of this frontier becomes work items, walked after
+                // everything the refinement of the best nodes produces
+                const int64_t rest = np - keep;
+                MSP_TRY(c->left_u.grow((size_t)(nleft + rest) * k, st));
+                MSP_TRY(c->left_meta.grow((size_t)(nleft + rest) * sizeof(int4), st));
+                MSP_TRY(launch_frontier_items(c->fr[cur].view(), c->order.as<int64_t>() + keep, rest, k, L,
+                                              c->left_u.as<int8_t>() + nleft * k, c->left_meta.as<int4>() + nleft,
+                                              st));
+                left.emplace_back(nleft, rest);
+                nleft += rest;
+                // the best nodes, back in depth-first order, as the next frontier
+                MSP_TRY(c->top_idx.ensure((size_t)keep * sizeof(int64_t)));
+                size_t tb = 0;
+                MSP_TRY(sort_idx_asc(nullptr, &tb, c->order.as<int64_t>(), c->top_idx.as<int64_t>(), keep, st));
+                MSP_TRY(c->sort_tmp.ensure(tb));
+                tb = c->sort_tmp.cap;
+                MSP_TRY(sort_idx_asc(c->sort_tmp.p, &tb, c->order.as<int64_t>(), c->top_idx.as<int64_t>(), keep, st));
+                const int nxt = (cur + 1) % 3, oth = (cur + 2) % 3;
+                MSP_TRY(launch_gather_frontier(c->fr[cur].view(), c->top_idx.as<int64_t>(), keep, c->fr[nxt].view(), k,
+                                               ws, st));
+                int a = nxt;
+                int64_t n2 = keep;
+                int L2 = L;
+                rc = expand(a, oth, n2, L2, [&](int64_t n_, int L_) { return n_ >= target || L_ <= L_stop; });
+                if (rc != MSP_OK) return rc;
+                ++stages;
+                const bool deeper = L2 < L;  // false: the next level would not fit the buffers
+                cur = a;
+                np = n2;
+                L = L2;
+                if (np > 1) {
+                    rc = order_frontier(cur, np, L);
+                    if (rc != MSP_OK) return rc;
+                }
+                if (!deeper || np == 0) break;
+            }
+        }
+        MSP_TRY(hipEventRecord(c->ev[7], st));
+    }
+    const bool use_order = ordered && np > 1;
+
+    // ---- subtree walk (levels L0-1 .. 0) ----
+    int wblock = walk_block_for(dimp, k, L0);
     if (p.block != 0 && wblock != 0) wblock = std::min(wblock, p.block);
     if (wblock == 0) return MSP_E_UNSUPPORTED;
     const int muc_len = walk_muc_len(k);
@@ -381,48 +516,27 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
                              c->g_muc.as<double>(), c->g_coff.as<int>(), st));
     const int64_t nwalk = (int64_t)c->num_cus * wblock;
     MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));
-    const int64_t pcap = np + std::max<int64_t>(256 * nwalk, 1 << 22);
+    const int64_t ninit = np + nleft;  // roots with stored w, then prefix-only items
+    const int64_t pcap = ninit + std::max<int64_t>(256 * nwalk, 1 << 22);
     MSP_TRY(c->pool_u.ensure((size_t)pcap * k));
     MSP_TRY(c->pool_meta.ensure((size_t)pcap * sizeof(int4)));
     MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));
     Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), pcap};
-    c->last_cur = cur;
-    c->last_np = np;
-    c->last_L = L;
-    c->last_k = k;
-    c->last_dim = dim;
-    c->last_ws = ws;
-    c->last_m = m;
-    c->last_R = R;
-    // ---- root order for first-solution search ----
-    const bool ordered = order != MSP_PLAIN && np > 1;
-    if (ordered) {
-        MSP_TRY(hipEventRecord(c->ev[6], st));
-        MSP_TRY(c->feat.ensure((size_t)np * kNumFeat * sizeof(float)));
-        MSP_TRY(c->key.ensure((size_t)np * sizeof(float)));
-        MSP_TRY(c->key_out.ensure((size_t)np * sizeof(float)));
-        MSP_TRY(c->idx_in.ensure((size_t)np * sizeof(int64_t)));
-        MSP_TRY(c->order.ensure((size_t)np * sizeof(int64_t)));
-        FeatArgs fa{k, dim, m, L, ws, c->fr[cur].view(), np, c->gs_mu.as<double>(), c->gs_beta.as<double>(), R,
-                    c->feat.as<float>()};
-        MSP_TRY(launch_root_features(fa, st));
-        if (order == MSP_LEARNED)
-            MSP_TRY(launch_mlp_score(c->w_q.as<float>(), c->feat.as<float>(), np, c->key.as<float>(), st));
-        else
-            MSP_TRY(launch_disc_keys(c->feat.as<float>(), np, k - L, c->key.as<float>(), st));
-        size_t tb = 0;
-        MSP_TRY(sort_scores_desc(nullptr, &tb, c->key.as<float>(), c->key_out.as<float>(), c->idx_in.as<int64_t>(),
-                                 c->order.as<int64_t>(), np, st));
-        MSP_TRY(c->sort_tmp.ensure(tb));
-        tb = c->sort_tmp.cap;
-        MSP_TRY(sort_scores_desc(c->sort_tmp.p, &tb, c->key.as<float>(), c->key_out.as<float>(),
-                                 c->idx_in.as<int64_t>(), c->order.as<int64_t>(), np, st));
-        MSP_TRY(hipEventRecord(c->ev[7], st));
-    }
-    if (np > 0) {
+    if (ninit > 0) {
         MSP_TRY(launch_pool_init(c->fr[cur].view(), np, k, L, pool, st));
-        const unsigned long long qt = (unsigned long long)np;
-        const long long pend = (long long)np;
+        // leftovers of the refinement stages, latest stage first
+        int64_t pos = np;
+        for (size_t s = left.size(); s-- > 0;) {
+            const int64_t off = left[s].first, cnt = left[s].second;
+            MSP_TRY(hipMemcpyAsync(pool.u + pos * k, c->left_u.as<int8_t>() + off * k, (size_t)cnt * k,
+                                   hipMemcpyDeviceToDevice, st));
+            MSP_TRY(hipMemcpyAsync(pool.meta + pos, c->left_meta.as<int4>() + off, (size_t)cnt * sizeof(int4),
+                                   hipMemcpyDeviceToDevice, st));
+            pos += cnt;
+        }
+        MSP_TRY(launch_fill_int(pool.ready + np, nleft, 1, st));
+        const unsigned long long qt = (unsigned long long)ninit;
+        const long long pend = (long long)ninit;
         MSP_TRY(hipMemcpyAsync(&ctl->qtail, &qt, sizeof(qt), hipMemcpyHostToDevice, st));
         MSP_TRY(hipMemcpyAsync(&ctl->pending, &pend, sizeof(pend), hipMemcpyHostToDevice, st));
         WalkArgs wa{};
@@ -430,7 +544,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.dim = dim;
         wa.n = n;
         wa.m = m;
-        wa.L = L;
+        wa.L = L0;
         wa.g_bh = c->g_bh.as<double>();
         wa.g_muc = c->g_muc.as<double>();
         wa.g_coff = c->g_coff.as<int>();
@@ -443,7 +557,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.nroots = np;
         wa.root_w = c->fr[cur].w.as<double>();
         wa.root_l = c->fr[cur].l.as<double>();
-        wa.order = ordered ? c->order.as<int64_t>() : nullptr;
+        wa.order = use_order ? c->order.as<int64_t>() : nullptr;
         wa.sol_u = sol_u;
         wa.head = &ctl->qhead;
         wa.tail = &ctl->qtail;
@@ -480,10 +594,13 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         stats->nodes = (int64_t)h.counters[1];
         stats->expansions = (int64_t)h.counters[2];
         stats->leaves = (int64_t)h.counters[3];
-        stats->roots = np;
+        stats->roots = np0;
+        stats->stages = stages;
+        stats->root_level = L;
+        stats->initial_items = ninit;
         stats->items = (int64_t)h.counters[4];
         stats->block = wblock;
-        stats->split_depth = k - L;
+        stats->split_depth = k - L0;
         stats->k = k;
         stats->gs_ms = elapsed(c->ev[0], c->ev[1]);
         stats->rootgen_ms = elapsed(c->ev[2], c->ev[3]);

@@ -119,6 +119,11 @@ int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
 int walk_max_level(int dimp, int k);         // largest split level whose walker fits in LDS
 
 hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
+hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws,
+                                  hipStream_t st);
+hipError_t launch_frontier_items(Frontier src, const int64_t *idx, int64_t n, int k, int L, int8_t *iu, int4 *imeta,
+                                 hipStream_t st);
+hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
 
 // ---- root orders and the root-scoring MLP (order.hip) ----
 constexpr int kNumFeat = 16;      // features per root
@@ -169,6 +174,7 @@ hipError_t launch_bf16_round(const float *master, float *wq, hipStream_t st);
 hipError_t launch_count_pos(const uint8_t *label, int64_t count, unsigned long long *npos, hipStream_t st);
 hipError_t sort_scores_desc(void *temp, size_t *temp_bytes, const float *key_in, float *key_out, int64_t *idx_in,
                             int64_t *idx_out, int64_t n, hipStream_t st);
+hipError_t sort_idx_asc(void *temp, size_t *temp_bytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t *keys_out, int32_t *idx,
                         int32_t *perm, int64_t n, unsigned long long seed, int epoch, hipStream_t st);
 

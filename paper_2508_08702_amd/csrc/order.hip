@@ -449,6 +449,11 @@ hipError_t sort_scores_desc(void *temp, size_t *temp_bytes, const float *key_in,
                                                         0, 32, st);
 }
 
+// Ascending sort of indices (restores depth-first order of a selection).
+hipError_t sort_idx_asc(void *temp, size_t *temp_bytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
+    return hipcub::DeviceRadixSort::SortKeys(temp, *temp_bytes, in, out, (int)n, 0, 64, st);
+}
+
 hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t *keys_out, int32_t *idx,
                         int32_t *perm, int64_t n, unsigned long long seed, int epoch, hipStream_t st) {
     if (temp == nullptr)

@@ -137,7 +137,58 @@ __global__ void pool_init_kernel(Frontier f, int64_t nroots, int k, int L, Pool 
     for (int64_t j = nroots + i; j < pool.cap; j += (int64_t)gridDim.x * blockDim.x) pool.ready[j] = 0;
 }
 
+// Copy frontier records idx[0..n) of src into dst[0..n) (one wave per record).
+__global__ void gather_frontier_kernel(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    const int64_t s = idx[r];
+    for (int j = lane; j < ws; j += 64) dst.w[r * ws + j] = src.w[s * ws + j];
+    for (int j = lane; j < k; j += 64) dst.u[r * k + j] = src.u[s * k + j];
+    if (lane == 0) {
+        dst.l[r] = src.l[s];
+        dst.tz[r] = src.tz[s];
+    }
+}
+
+// Work items "enumerate level L-1 below the prefix" for records idx[0..n) of
+// a frontier at level L (the walker recomputes w and the norms from u).
+__global__ void frontier_items_kernel(Frontier src, const int64_t *idx, int64_t n, int k, int L, int8_t *iu,
+                                      int4 *imeta) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t s = idx[r];
+    for (int j = 0; j < k; ++j) iu[r * k + j] = j >= L ? src.u[s * k + j] : (int8_t)0;
+    imeta[r] = make_int4(L - 1, 0, 8 | (src.tz[s] ? 4 : 0), 0);
+}
+
+__global__ void fill_int_kernel(int *p, int64_t n, int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws,
+                                  hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_frontier_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, src, idx, n, dst, k,
+                       ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontier_items(Frontier src, const int64_t *idx, int64_t n, int k, int L, int8_t *iu, int4 *imeta,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(frontier_items_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, idx, n, k, L, iu, imeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st) {
     if (a.np <= 0) return hipSuccess;

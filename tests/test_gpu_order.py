@@ -179,3 +179,38 @@ def test_learned_order_needs_a_model(M):
             M.msp_model_set(c, np.full(N.NPARAM, np.nan, dtype=np.float32))
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("m,seed,feasible", [(6, 31, True), (7, 32, True), (6, 33, False), (7, 34, False)])
+def test_refined_first_search_stays_exhaustive(M, ctx, order, m, seed, feasible):
+    """Best-first refinement reorders the tree but covers it exactly once:
+    with refinement forced through several stages, first mode returns an
+    oracle solution where there is one, and where there is none (d_0 beyond
+    the row sum) it walks exactly the nodes of the plain exhaustive run."""
+    M.msp_model_init(ctx, 6)
+    inst = mi.cornuejols_dawande(m, seed)
+    A_np, d_np = inst.A, inst.d.copy()
+    if not feasible:
+        d_np[0] = int(A_np[0].astype(np.int64).sum()) + 1
+    P = L.prepare(A_np, d_np)
+    ref = E.enumerate_prepared(P, split=6, threads=8)
+    assert (ref.n_found > 0) == feasible
+    A, d, Bk = _dev(A_np), _dev(d_np), _dev(P.basis)
+    base = M.msp_params_default(time_cap_ms=60000.0)
+    plain = M.msp_enumerate(ctx, A, d, Bk, params=base)
+    assert plain.status == M.MSP_OK and plain.n_found == ref.n_found
+    prm = M.msp_params_default(time_cap_ms=60000.0, target_roots=2048, refine_keep=64)
+    print(f"  refined first m={m} seed={seed} order={order} oracle solutions={ref.n_found}", flush=True)
+    r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=M.MSP_FIRST, order=order, cap=64)
+    assert r.status == M.MSP_OK
+    assert r.stats["stages"] >= 1 and r.stats["root_level"] < P.k - r.stats["split_depth"]
+    if not feasible:
+        assert r.n_found == 0
+        for key in ("evals", "nodes", "expansions", "leaves"):
+            assert r.stats[key] == plain.stats[key], key
+    else:
+        x = r.x.cpu().numpy()
+        assert 1 <= x.shape[0] and E.verify(A_np, d_np, x)
+        rows = {tuple(row) for row in ref.solutions}
+        assert all(tuple(row) in rows for row in x)
