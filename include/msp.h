@@ -193,6 +193,24 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
                     const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
                     int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
 
+/* Autotuner (a project addition).  Reduces the `batch` tuning instances once
+ * (as msp_solve_batch does), then for each candidate root count -- 128, 256,
+ * 512, 1024 and 2048 roots per CU for MSP_ALL; 4096, 16384 and 65536 per CU
+ * for MSP_FIRST -- enumerates every instance with *base and target_roots set
+ * to the candidate, and times the enumeration (root generation, ordering and
+ * walk; device events).  *best = *base with the fastest candidate's
+ * target_roots.  points (may be NULL, room for 8) receives each candidate's
+ * target_roots and total milliseconds; *npoints their count.  The result set
+ * never depends on the candidate; only time does. */
+typedef struct {
+    int32_t target_roots;
+    int32_t status;          /* first non-OK status over the batch, or MSP_OK */
+    double ms;               /* summed enumeration time over the batch        */
+} msp_tune_point;
+int msp_autotune(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const int32_t *A_dev,
+                 const int64_t *d_dev, int mode, int order, const msp_params *base, msp_params *best,
+                 msp_tune_point *points, int *npoints, void *stream);
+
 /* ---- root traces and the root-scoring model (a project addition; none of
  * this is in the paper) ------------------------------------------------- */
 

@@ -42,7 +42,7 @@ MSP_MODEL_NPARAM = 5313
 EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_strerror",
-    "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
+    "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
     "msp_model_grad", "msp_train_params_default", "msp_model_train",
 )
 
@@ -87,6 +87,10 @@ class TrainParams(C.Structure):
                 ("seed", C.c_uint64), ("use_graph", C.c_int)]
 
 
+class TunePoint(C.Structure):
+    _fields_ = [("target_roots", C.c_int32), ("status", C.c_int32), ("ms", C.c_double)]
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_08702_amd.build`")
@@ -108,6 +112,9 @@ def _load() -> C.CDLL:
     lib.msp_solve_batch.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params), vp,
                                     C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(Stats), vp]
     lib.msp_solve_batch.restype = i32
+    lib.msp_autotune.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params),
+                                 C.POINTER(Params), C.POINTER(TunePoint), C.POINTER(i32), vp]
+    lib.msp_autotune.restype = i32
     lib.msp_root_trace.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.POINTER(Params), vp, vp, i64,
                                    C.POINTER(i64), C.POINTER(i64), C.POINTER(Stats), vp]
     lib.msp_root_trace.restype = i32
@@ -292,13 +299,7 @@ class BatchResult:
     rc: int           # MSP_OK, or the first non-OK instance status
 
 
-def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order: int = MSP_PLAIN,
-                    params: Params | None = None, cap: int = 1024) -> BatchResult:
-    """Reduce and enumerate a batch of instances of uneven shape.
-
-    As / ds: lists of int32 (m_i x n_i) and int64 (m_i) device tensors.  They
-    are packed into one buffer each (plain device copies) and described to
-    the library by element offsets; every instance gets ``cap`` output rows."""
+def _pack(ctx: Context, As: list, ds: list, cap: int):
     if len(As) != len(ds) or not As:
         raise ValueError("As and ds must be non-empty lists of equal length")
     dev = ctx.device
@@ -316,6 +317,34 @@ def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, or
         x_off += cap * n
     A_all = torch.cat([A.reshape(-1) for A in As])
     d_all = torch.cat([d.reshape(-1) for d in ds])
+    return desc, A_all, d_all, x_off
+
+
+def msp_autotune(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order: int = MSP_PLAIN,
+                 params: Params | None = None):
+    """Pick target_roots on tuning instances; returns (best Params, [(target_roots, status, ms), ...])."""
+    desc, A_all, d_all, _ = _pack(ctx, As, ds, 0)
+    p = params if params is not None else msp_params_default()
+    best = Params()
+    pts = (TunePoint * 8)()
+    npts = C.c_int(0)
+    rc = lib().msp_autotune(ctx.handle, len(As), desc, A_all.data_ptr(), d_all.data_ptr(), int(mode), int(order),
+                            C.byref(p), C.byref(best), pts, C.byref(npts), _stream_handle(ctx.device))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_autotune")
+    return best, [(pts[i].target_roots, pts[i].status, pts[i].ms) for i in range(npts.value)]
+
+
+def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order: int = MSP_PLAIN,
+                    params: Params | None = None, cap: int = 1024) -> BatchResult:
+    """Reduce and enumerate a batch of instances of uneven shape.
+
+    As / ds: lists of int32 (m_i x n_i) and int64 (m_i) device tensors.  They
+    are packed into one buffer each (plain device copies) and described to
+    the library by element offsets; every instance gets ``cap`` output rows."""
+    dev = ctx.device
+    desc, A_all, d_all, x_off = _pack(ctx, As, ds, cap)
+    b = len(As)
     x_all = torch.zeros(max(x_off, 1), dtype=torch.uint8, device=dev)
     nf = (C.c_int64 * b)()
     st = (C.c_int32 * b)()

@@ -757,6 +757,74 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
 }
 
 
+int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,
+                 int mode, int order, const msp_params *base, msp_params *best, msp_tune_point *points, int *npoints,
+                 void *stream) {
+    if (!c || batch < 1 || !desc || !A_dev || !d_dev || !best) return MSP_E_ARG;
+    if (mode != MSP_ALL && mode != MSP_FIRST) return MSP_E_ARG;
+    for (int i = 0; i < batch; ++i) {
+        const msp_batch_desc &e = desc[i];
+        if (e.m < 1 || e.n < 1 || e.m > e.n || e.n > MSP_MAX_N || e.A_off < 0 || e.d_off < 0) return MSP_E_ARG;
+    }
+    msp_params p;
+    msp_params_default(&p);
+    if (base) p = *base;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<LllDesc> h(batch);
+    size_t boff = 0;
+    int maxn = 0;
+    for (int i = 0; i < batch; ++i) {
+        h[i] = LllDesc{desc[i].m, desc[i].n, desc[i].A_off, desc[i].d_off, 0, (int64_t)boff, 0, 0, 0};
+        boff += (size_t)(desc[i].n + 1) * (desc[i].n + 1);
+        maxn = std::max(maxn, desc[i].n);
+    }
+    MSP_TRY(c->batch_basis.ensure(boff * sizeof(int64_t)));
+    int64_t *bases = c->batch_basis.as<int64_t>();
+    int rc = run_lll(c, h, A_dev, d_dev, bases, p, st);
+    if (rc != MSP_OK) return rc;
+    for (int i = 0; i < batch; ++i)
+        if (lll_status(h[i].status) != MSP_OK) return lll_status(h[i].status);
+    const int per_cu_all[] = {128, 256, 512, 1024, 2048};
+    const int per_cu_first[] = {4096, 16384, 65536};
+    const int *cand = mode == MSP_ALL ? per_cu_all : per_cu_first;
+    const int ncand = mode == MSP_ALL ? 5 : 3;
+    // first-solution tuning needs an output row per instance; exhaustive
+    // tuning counts only
+    MSP_TRY(c->trace_x.ensure((size_t)64 * (maxn > 0 ? maxn : 1)));
+    double best_ms = -1.0;
+    int best_t = 0;
+    for (int ci = 0; ci < ncand; ++ci) {
+        msp_params q = p;
+        q.target_roots = cand[ci] * c->num_cus;
+        q.split_depth = -1;
+        double tot = 0.0;
+        int st_first = MSP_OK;
+        for (int i = 0; i < batch; ++i) {
+            const msp_batch_desc &e = desc[i];
+            int64_t nf = 0;
+            msp_stats sti;
+            const int s = enumerate_impl(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off,
+                                         h[i].kout, mode, order, &q, c->trace_x.as<uint8_t>(), 64, &nf, &sti, stream);
+            if (s != MSP_OK && s != MSP_E_CAPACITY && st_first == MSP_OK) st_first = s;
+            if (s != MSP_OK && s != MSP_E_CAPACITY && s != MSP_E_TIMEOUT) return s;
+            tot += sti.rootgen_ms + sti.ordering_ms + sti.kernel_ms;
+        }
+        if (points && ci < 8) points[ci] = msp_tune_point{q.target_roots, st_first, tot};
+        if (st_first == MSP_OK && (best_ms < 0.0 || tot < best_ms)) {
+            best_ms = tot;
+            best_t = q.target_roots;
+        }
+    }
+    if (npoints) *npoints = ncand;
+    if (best_ms < 0.0) return MSP_E_TIMEOUT;  // no candidate finished every instance
+    *best = p;
+    best->target_roots = best_t;
+    best->split_depth = -1;
+    return MSP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Root traces and the root-scoring model.
 

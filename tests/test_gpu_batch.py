@@ -45,9 +45,9 @@ def _oracle(inst):
     return E.solve(inst.A, inst.d, split=6, threads=os.cpu_count() or 1)[1]
 
 
-def _run_batch(M, ctx, insts, **kw):
+def _run_batch(M, ctx, insts, params=None, **kw):
     print(f"  gpu batch of {len(insts)} seeds {insts[0].seed}..{insts[-1].seed}", flush=True)
-    prm = M.msp_params_default(time_cap_ms=60000.0)
+    prm = params if params is not None else M.msp_params_default(time_cap_ms=60000.0)
     r = M.msp_solve_batch(ctx, [_dev(i.A) for i in insts], [_dev(i.d) for i in insts], params=prm, **kw)
     torch.cuda.synchronize()
     return r
@@ -129,3 +129,21 @@ def test_batch_bad_arguments(M, ctx, batch):
         M.msp_solve_batch(ctx, [_dev(inst.A.T.copy())], [_dev(np.zeros(inst.n, np.int64))])
     with pytest.raises(ValueError):
         M.msp_solve_batch(ctx, [], [])
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(M, ctx, batch):
+    tune = mi.mixed_batch(range(3900, 3932))[:8]          # tuning seeds, disjoint from the batch
+    best, pts = M.msp_autotune(ctx, [_dev(i.A) for i in tune], [_dev(i.d) for i in tune],
+                               params=M.msp_params_default(time_cap_ms=60000.0))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert [p[0] for p in pts] == [c * cus for c in (128, 256, 512, 1024, 2048)]
+    assert all(p[1] == M.MSP_OK and p[2] > 0 for p in pts)
+    assert best.target_roots == min(pts, key=lambda p: p[2])[0] and best.split_depth == -1
+    insts = batch[:12]
+    tuned = _run_batch(M, ctx, insts, params=best)
+    plain = _run_batch(M, ctx, insts)
+    for i in range(len(insts)):
+        assert tuned.status[i] == plain.status[i] == M.MSP_OK
+        assert np.array_equal(E.sort_rows(tuned.x[i].cpu().numpy()), E.sort_rows(plain.x[i].cpu().numpy()))
+        for key in ("evals", "nodes", "expansions", "leaves"):
+            assert tuned.stats[i][key] == plain.stats[i][key], key
