@@ -12,7 +12,7 @@
  *
  * The level-t step (Section 2, "First/Second pruning condition", Alg. 1):
  *   y_t  = sum_{i>t} u_i mu_{i,t}          centre of level t is c = -y_t,
- *                                          summed from i = k-1 down to t+1
+ *                                          in the fixed order of centre() below
  *   x    = u_t + y_t
  *   l    = x^2 beta_t + l'                 ||w^(t)||^2 by the recurrence
  *   prune (return) when l > R (1 + eps)    R = (n+1) r_max^2
@@ -30,8 +30,10 @@
  *   - the sign symmetry v <-> -v is broken: while every u_i above t is 0,
  *     only u_t = 0, 1, 2, ... is tried, and the first Hoelder failure there
  *     ends the level (its mirror image fails as well);
- *   - the centre sum runs from the top level down, the order in which the
- *     search fixes the u_i;
+ *   - the centre sum has a fixed order: with p = k-1-i (p = 0 for the top
+ *     level), term p goes to partial sum s_(p mod 8), each partial sum is
+ *     accumulated from the top level down starting at 0, and
+ *     y = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
  *   - eps = 1e-9 relative slack on both tests (solutions lie exactly on the
  *     l2 bound);
  *   - the r_max coordinate is the last one (index n): a solution has
@@ -192,12 +194,22 @@ static int zig_next(int o, int s) {
     return -o + s;
 }
 
+/* Centre sum y_t = sum_{i>t} u_i mu_{i,t} in the order stated above. */
+static double centre(const orc_args *a, const int *u, int t) {
+    const int k = a->k;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = k - 1; i > t; --i) {
+        const int p = k - 1 - i;
+        s[p % 8] = s[p % 8] + (double)u[i] * a->mu[(int64_t)i * k + t];
+    }
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, int topzero) {
     const orc_args *a = W->a;
-    const int k = a->k, dim = a->dim;
+    const int dim = a->dim;
     double w[ORC_MAXDIM];
-    double y = 0.0;
-    for (int i = k - 1; i > t; --i) y += (double)W->u[i] * a->mu[(int64_t)i * k + t];
+    const double y = centre(a, W->u, t);
     const double c = -y;
     const double bound = a->R * (1.0 + a->eps);
     int u1, s, off = 0, onedir, dir;

@@ -14,7 +14,7 @@ Root features (a project addition for ordering the roots; the definitions
 below are the specification, written out in FP64 and stored as float32):
 for root r at level L with prefix u_{k-1..L}, partial norm l and projected
 vector w, R = n + 1, and per level j the centre y_j = sum_{i>j} u_i mu_{i,j}
-(top level first) and the zig-zag rank of u_j (its index in the sequence
+(the enumerator's fixed summation order) and the zig-zag rank of u_j (its index in the sequence
 u1, u1+s, u1-s, u1+2s, ... of next(), or u_j itself while every higher u is
 zero):
     0 l/R            1 l/||w||_1 (0 if w = 0)   2 min(||w||_inf, 4)/4
@@ -46,6 +46,18 @@ class Root:
     w: np.ndarray  # float64 (dim,)
 
 
+def centre(P, u, t: int) -> float:
+    """y_t = sum_{i>t} u_i mu_{i,t} in the fixed order of the enumerator:
+    term p = k-1-i goes to partial sum s[p mod 8], each accumulated from the
+    top level down from 0.0; y = ((s0+s1)+(s2+s3)) + ((s4+s5)+(s6+s7))."""
+    k = P.k
+    s = [0.0] * 8
+    for i in range(k - 1, t, -1):
+        p = k - 1 - i
+        s[p % 8] = s[p % 8] + float(u[i]) * float(P.mu[i, t])
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))
+
+
 def _zig_next(off: int, s: int) -> int:
     if off == 0:
         return s
@@ -61,14 +73,12 @@ def roots_dfs(P, split: int, eps: float = E.EPS, hoelder: bool = True, onedir_cu
     assert 1 <= split <= k - 1
     R = float(P.n + 1)
     bound = R * (1.0 + eps)
-    mu, beta, bhat = P.mu, P.beta, P.bhat
+    beta, bhat = P.beta, P.bhat
     u = [0] * k
     out: list[Root] = []
 
     def level(t, wpar, lpar, topzero):
-        y = 0.0
-        for i in range(k - 1, t, -1):
-            y = y + float(u[i]) * float(mu[i, t])
+        y = centre(P, u, t)
         c = -y
         if topzero:
             u1, s, onedir, dr = 0, 1, True, 1
@@ -128,7 +138,7 @@ def features(P, roots, L: int) -> np.ndarray:
     """float32 (len(roots), 16) per the definitions in the module docstring."""
     k, dim, m = P.k, P.dim, P.m
     R = float(P.n + 1)
-    mu, beta = P.mu, P.beta
+    beta = P.beta
     F = np.zeros((len(roots), NFEAT), dtype=np.float64)
     lv = float(k - L)
     for r, rt in enumerate(roots):
@@ -136,9 +146,7 @@ def features(P, roots, L: int) -> np.ndarray:
         ranks, tz = [], True
         xL = 0.0
         for j in range(k - 1, L - 1, -1):
-            y = 0.0
-            for i in range(k - 1, j, -1):
-                y = y + float(u[i]) * float(mu[i, j])
+            y = centre(P, u, j)
             ranks.append(zigzag_rank(u[j], y, tz))
             if j == L:
                 xL = float(u[j]) + y
