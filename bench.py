@@ -55,15 +55,18 @@ def walk_source_hash() -> str:
     return h.hexdigest()
 
 WORKLOADS = {
-    # name: (description, list of (m, D, seed))
+    # name: (description, list of (m, D, seed), generator)
     "m9": ("12 planted instances m=9, n=80, 4 each D=50/100/200 (seeds 4500-4511), exhaustive",
-           [(9, (50, 100, 200)[i // 4], 4500 + i) for i in range(12)]),
+           [(9, (50, 100, 200)[i // 4], 4500 + i) for i in range(12)], "planted"),
     "m9-d200": ("4 planted instances m=9, n=80, D=200 (seeds 4508-4511), exhaustive",
-                [(9, 200, 4508 + i) for i in range(4)]),
+                [(9, 200, 4508 + i) for i in range(4)], "planted"),
     "m9-1": ("1 planted instance m=9, n=80, D=200 (seed 4508), exhaustive",
-             [(9, 200, 4508)]),
+             [(9, 200, 4508)], "planted"),
     "m8": ("4 planted instances m=8, n=70, D=100 (seeds 4000-4003), exhaustive",
-           [(8, 100, 4000 + i) for i in range(4)]),
+           [(8, 100, 4000 + i) for i in range(4)], "planted"),
+    "cd8": ("4 Cornuejols-Dawande instances m=8, n=70, D=100, d = floor(row sums / 2) "
+            "(seeds 6000-6003), exhaustive (mostly infeasible: empty output after the full walk)",
+            [(8, 100, 6000 + i) for i in range(4)], "cd"),
 }
 
 
@@ -189,8 +192,11 @@ def main():
     import msp_instances as mi
     import paper_2508_08702_amd as M
 
-    desc, spec = WORKLOADS[args.workload]
-    insts = [mi.msp_class(m, D, s) for (m, D, s) in spec]
+    desc, spec, gen = WORKLOADS[args.workload]
+    if gen == "cd":
+        insts = [mi.cornuejols_dawande(m, s, D) for (m, D, s) in spec]
+    else:
+        insts = [mi.msp_class(m, D, s) for (m, D, s) in spec]
     dev = torch.device("cuda", 0)
     dev_in = [(torch.from_numpy(i.A).to(dev), torch.from_numpy(i.d).to(dev)) for i in insts]
     ctx = M.Context(0)
@@ -206,8 +212,10 @@ def main():
             if r.status != M.MSP_OK:
                 raise RuntimeError(f"enumeration status {r.status} ({M.msp_strerror(r.status)})")
             xs = r.x.cpu().numpy().astype(np.int64)
-            if xs.shape[0] == 0 or not np.all(xs @ inst.A.T.astype(np.int64) == inst.d[None, :]):
+            if xs.shape[0] and not np.all(xs @ inst.A.T.astype(np.int64) == inst.d[None, :]):
                 raise RuntimeError("a returned row does not satisfy A x = d")
+            if gen == "planted" and xs.shape[0] == 0:
+                raise RuntimeError("the planted solution was not found")
             st = r.stats
             tot_nodes += st["nodes"]
             tot_evals += st["evals"]

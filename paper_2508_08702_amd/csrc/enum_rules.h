@@ -4,8 +4,14 @@
 // Centre and partial norm are evaluated with every product and sum rounded
 // on its own (no fused multiply-add), in a fixed order, so that these scalar
 // recurrences -- which decide the l2 pruning -- are reproducible bit for bit:
-//   y_t = sum_{i = k-1 down to t+1} u_i mu_{i,t}     (centre c_t = -y_t)
-//   l   = (x * x) * beta_t + l'                       (x = u_t + y_t)
+//   y_t = sum_{i>t} u_i mu_{i,t}   (centre c_t = -y_t): term p = k-1-i (p = 0
+//         is the top level) goes to partial sum s_(p mod 8), each partial
+//         sum runs from the top level down starting at 0, and
+//         y_t = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+//   l   = (x * x) * beta_t + l'   (x = u_t + y_t)
+// Eight interleaved sums make the dependent chain eight times shorter than
+// one running sum; any fixed order serves, as long as it is the same
+// everywhere.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +25,28 @@ __device__ __forceinline__ double mul_rn(double a, double b) { return a * b; }
 
 __device__ __forceinline__ double partial_norm(double x, double beta, double lpar) {
     return add_rn(mul_rn(mul_rn(x, x), beta), lpar);
+}
+
+__device__ __forceinline__ double combine8(const double (&s)[8]) {
+    return add_rn(add_rn(add_rn(s[0], s[1]), add_rn(s[2], s[3])), add_rn(add_rn(s[4], s[5]), add_rn(s[6], s[7])));
+}
+
+// Centre sum for a prefix in natural level order (u[i] = u_i) and mu row-major
+// (mu[i * k + t] = mu_{i,t}).
+__device__ __forceinline__ double centre_natural(const int8_t *u, const double *mu, int k, int t) {
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int nt = k - 1 - t;
+    for (int p0 = 0; p0 < nt; p0 += 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int p = p0 + r;
+            if (p < nt) {
+                const int i = k - 1 - p;
+                s[r] = add_rn(s[r], mul_rn((double)u[i], mu[(size_t)i * k + t]));
+            }
+        }
+    }
+    return combine8(s);
 }
 
 // Zig-zag state of one level: values u1, u1+s, u1-s, u1+2s, ... around the

@@ -32,7 +32,8 @@ __device__ __forceinline__ float bf16_rne(float x) {
 
 // ---------------------------------------------------------------------------
 // Root features.  For root r at level L with prefix u_{k-1..L}:
-//   per level j (top first): centre y_j (top-down, unfused), x_j = u_j + y_j,
+//   per level j (top first): centre y_j (the enumeration's fixed order),
+//   x_j = u_j + y_j,
 //   zig-zag rank of u_j (its position in the sequence u1, u1+s, u1-s, ...,
 //   or u_j itself while every higher u is zero).
 //   f0  l / R                      f8  min(max |u_j|, 4) / 4
@@ -57,8 +58,7 @@ __global__ void root_feat_kernel(FeatArgs a) {
     bool tz = true;
     double xL = 0.0, eL = 0.0;
     for (int j = k - 1; j >= L; --j) {
-        double y = 0.0;
-        for (int i = k - 1; i > j; --i) y = add_rn(y, mul_rn((double)u[i], a.mu[(size_t)i * k + j]));
+        const double y = centre_natural(u, a.mu, k, j);
         const int uj = u[j];
         int rank;
         if (tz) {

@@ -25,8 +25,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         const double *wp = a.par.w + p * ws;
         const double lpar = a.par.l[p];
         const bool tz = a.par.tz[p] != 0;
-        double y = 0.0;
-        for (int i = k - 1; i > t; --i) y = add_rn(y, mul_rn((double)up[i], a.mu[(size_t)i * k + t]));
+        const double y = centre_natural(up, a.mu, k, t);
         const Zig z = zig_init(y, tz);
         int u = z.u1;
         bool onedir = tz;

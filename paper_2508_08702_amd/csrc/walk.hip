@@ -61,13 +61,15 @@ __device__ __forceinline__ long long ld_rlx(const long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// centre sum of level t, top level first (8 levels per chunk).  my_u[p] holds
-// u_{k-1-p}; col[p] = mu_{k-1-p,t}, zero beyond the column's k-1-t entries.
-// The loads of chunk c+1 are issued before chunk c is summed.
+// Centre sum of level t in the fixed order (term p = k-1-i into partial sum
+// p mod 8): one chunk of 8 levels feeds the 8 partial sums.  my_u[p] holds
+// u_{k-1-p}; col[p] = mu_{k-1-p,t}, zero beyond the column's k-1-t entries
+// (a zero term leaves a partial sum unchanged).  The loads of chunk c+1 are
+// issued before chunk c is summed.
 __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, const double *col) {
     const int nt = k - 1 - t;
-    double y = 0.0;
-    if (nt <= 0) return y;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (nt <= 0) return combine8(s);
     uint2 uu = *reinterpret_cast<const uint2 *>(my_u);
     double2 m0 = *reinterpret_cast<const double2 *>(col);
     double2 m1 = *reinterpret_cast<const double2 *>(col + 2);
@@ -80,21 +82,21 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
         const double2 n1 = *reinterpret_cast<const double2 *>(col + cn + 2);
         const double2 n2 = *reinterpret_cast<const double2 *>(col + cn + 4);
         const double2 n3 = *reinterpret_cast<const double2 *>(col + cn + 6);
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.x), m0.x));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 8), m0.y));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 16), m1.x));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.x >> 24), m1.y));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.y), m2.x));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 8), m2.y));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 16), m3.x));
-        y = add_rn(y, mul_rn((double)(int8_t)(uu.y >> 24), m3.y));
+        s[0] = add_rn(s[0], mul_rn((double)(int8_t)(uu.x), m0.x));
+        s[1] = add_rn(s[1], mul_rn((double)(int8_t)(uu.x >> 8), m0.y));
+        s[2] = add_rn(s[2], mul_rn((double)(int8_t)(uu.x >> 16), m1.x));
+        s[3] = add_rn(s[3], mul_rn((double)(int8_t)(uu.x >> 24), m1.y));
+        s[4] = add_rn(s[4], mul_rn((double)(int8_t)(uu.y), m2.x));
+        s[5] = add_rn(s[5], mul_rn((double)(int8_t)(uu.y >> 8), m2.y));
+        s[6] = add_rn(s[6], mul_rn((double)(int8_t)(uu.y >> 16), m3.x));
+        s[7] = add_rn(s[7], mul_rn((double)(int8_t)(uu.y >> 24), m3.y));
         uu = nu;
         m0 = n0;
         m1 = n1;
         m2 = n2;
         m3 = n3;
     }
-    return y;
+    return combine8(s);
 }
 
 }  // namespace

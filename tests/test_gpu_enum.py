@@ -181,3 +181,24 @@ def test_bad_arguments(M, ctx):
     prm = M.msp_params_default(split_depth=P.k)
     r = M.msp_enumerate(ctx, A, d, Bs, params=prm, raise_on_error=False)
     assert r.status == M.MSP_E_ARG
+
+
+@pytest.mark.parametrize("seed", [6000, 6003])
+def test_cornuejols_dawande_instances(M, ctx, seed):
+    """The original generator, d_i = floor(sum_j a_ij / 2), m=7, n=60: the
+    exhaustive walk on the oracle's basis gives the oracle's set and search
+    counters, and the whole GPU path (GPU LLL basis) the same set."""
+    import os
+    inst = mi.cornuejols_dawande(7, seed)
+    P = L.prepare(inst.A, inst.d)
+    ref = E.enumerate_prepared(P, split=8, threads=os.cpu_count() or 1)
+    r, x = _gpu_enum(M, ctx, inst, P)
+    assert r.status == M.MSP_OK and r.n_found == ref.n_found
+    assert np.array_equal(x, ref.solutions)
+    for key in ("evals", "nodes", "expansions", "leaves"):
+        assert r.stats[key] == getattr(ref, key), key
+    A, d = _dev(inst.A), _dev(inst.d)
+    Bk = M.msp_reduce(ctx, A, d)
+    r2 = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(time_cap_ms=60000.0))
+    assert r2.status == M.MSP_OK
+    assert np.array_equal(E.sort_rows(r2.x.cpu().numpy()), ref.solutions)
