@@ -113,3 +113,20 @@ def count_dp(A, d) -> int:
         shifted[a:, b:] = tab[: S1 + 1 - a, : S2 + 1 - b]
         tab = tab + shifted
     return int(tab[S1, S2])
+
+
+def brute_force_bounded(A, d, r) -> np.ndarray:
+    """All x with 0 <= x_j <= r_j and A x = d, by trying every point of the
+    box (prod (r_j + 1) points; small boxes only).  Rows sorted
+    lexicographically, uint8."""
+    import itertools
+    A = np.asarray(A, dtype=np.int64)
+    d = np.asarray(d, dtype=np.int64)
+    r = [int(v) for v in r]
+    total = 1
+    for v in r:
+        total *= v + 1
+    assert total <= 1 << 22, "box too large for brute force"
+    pts = np.array(list(itertools.product(*[range(v + 1) for v in r])), dtype=np.int64)
+    ok = np.all(pts @ A.T == d[None, :], axis=1)
+    return pts[ok].astype(np.uint8)

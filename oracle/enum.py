@@ -36,6 +36,7 @@ class _Args(C.Structure):
         ("cap", C.c_int64), ("time_cap_s", C.c_double),
         ("sol", C.c_void_p), ("n_found", C.c_void_p), ("counters", C.c_void_p),
         ("level_counts", C.c_void_p), ("n_roots", C.c_void_p), ("timed_out", C.c_void_p),
+        ("cvec", C.c_void_p),
     ]
 
 
@@ -82,8 +83,9 @@ def enumerate_prepared(P: lattice.Prepared, *, split: int = 0, threads: int = 1,
                        mode: str = "all", cap: int = 1 << 16, hoelder: bool = True,
                        onedir: bool = True, eps: float = EPS, time_cap_s: float = 0.0,
                        level_counts: bool = False) -> Result:
-    """Enumerate every v in the kernel lattice with ||v||_inf <= 1 and
-    v_n = 1 (each solution once) on the basis held by ``P``."""
+    """Enumerate every v in the kernel lattice with ||v||_inf <= r_max and
+    v_n = r_max (each solution once) on the basis held by ``P`` (binary:
+    r_max = 1)."""
     lib = _load()
     k, dim, m, n = P.k, P.dim, P.m, P.n
     bhat = np.ascontiguousarray(P.bhat, dtype=np.float64)
@@ -102,9 +104,11 @@ def enumerate_prepared(P: lattice.Prepared, *, split: int = 0, threads: int = 1,
     a.k, a.dim, a.m, a.n = k, dim, m, n
     a.bhat, a.mu, a.beta = bhat.ctypes.data, mu.ctypes.data, beta.ctypes.data
     a.basis, a.A, a.d = basis.ctypes.data, A.ctypes.data, d.ctypes.data
-    a.R = float(n + 1)  # (n+1) r_max^2 with r_max = 1
+    a.R = float((n + 1) * P.rmax * P.rmax)  # (n+1) r_max^2
     a.eps = eps
-    a.rmax = 1
+    a.rmax = int(P.rmax)
+    cvec = None if P.cvec is None else np.ascontiguousarray(P.cvec, dtype=np.int64)
+    a.cvec = cvec.ctypes.data if cvec is not None else None
     a.hoelder = int(hoelder)
     a.onedir = int(onedir)
     a.mode = 1 if mode == "first" else 0
@@ -128,17 +132,19 @@ def enumerate_prepared(P: lattice.Prepared, *, split: int = 0, threads: int = 1,
                   level_counts=lvl)
 
 
-def solve(A, d, *, N: int = lattice.DEFAULT_N, **kw) -> tuple[lattice.Prepared, Result]:
-    """Steps 1-4 of Algorithm 1 plus the enumeration."""
-    P = lattice.prepare(A, d, N=N)
+def solve(A, d, *, N: int = lattice.DEFAULT_N, r=None, **kw) -> tuple[lattice.Prepared, Result]:
+    """Steps 1-4 of Algorithm 1 plus the enumeration (r: upper bounds)."""
+    P = lattice.prepare(A, d, N=N, r=r)
     return P, enumerate_prepared(P, **kw)
 
 
-def verify(A, d, X) -> bool:
-    """Independent exact check that every row x of X is binary and A x = d."""
+def verify(A, d, X, r=None) -> bool:
+    """Independent exact check that every row x of X satisfies 0 <= x <= r
+    (binary when r is None) and A x = d."""
     X = np.asarray(X)
     if X.size == 0:
         return True
-    if not np.all((X == 0) | (X == 1)):
+    hi = 1 if r is None else np.asarray(r, dtype=np.int64)[None, :]
+    if not np.all((X.astype(np.int64) >= 0) & (X.astype(np.int64) <= hi)):
         return False
     return bool(np.all(X.astype(np.int64) @ np.asarray(A, dtype=np.int64).T == np.asarray(d, dtype=np.int64)[None, :]))

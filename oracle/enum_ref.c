@@ -37,8 +37,8 @@
  *   - eps = 1e-9 relative slack on both tests (solutions lie exactly on the
  *     l2 bound);
  *   - the r_max coordinate is the last one (index n): a solution has
- *     |v_n| = 1 and |v_j| <= 1, and x_j = (v_j + 1) / 2 after normalising
- *     the sign so that v_n = +1.
+ *     |v_n| = r_max and |v_j| <= r_max (Thm 1), and x_j = (v_j + r_max) / (2 c_j)
+ *     after normalising the sign so that v_n = +r_max (binary: r_max = c_j = 1).
  *
  * Counters: eval = a candidate whose l was computed; node = a candidate
  * that passed the l2 test; expansion = a node that passed the Hoelder test
@@ -78,6 +78,8 @@ typedef struct {
     int64_t *level_counts;  /* optional, k x 3: evals, nodes, expansions      */
     int64_t *n_roots;       /* number of subtree roots generated             */
     int *timed_out;
+    const int64_t *cvec;    /* n, c_j = r_max / r_j for bounded variables;
+                             * NULL: binary (r_max = c_j = 1)                 */
 } orc_args;
 
 /* Subtree roots, stored flat: root r has prefix u[r*k + i] (i >= level),
@@ -130,8 +132,11 @@ static void leaf(orc_walker *W) {
     for (int j = 0; j < n; ++j) {
         int64_t vj = sg * v[j];
         if (vj > a->rmax || vj < -a->rmax) return;
-        if (vj != 1 && vj != -1) return;   /* binary case: v_j = 2 x_j - 1 */
-        x[j] = (uint8_t)((vj + 1) / 2);
+        /* v_j = 2 c_j x_j - r_max (eq. (2) with v_n = r_max) */
+        const int64_t cj = a->cvec ? a->cvec[j] : 1;
+        const int64_t tj = vj + a->rmax;
+        if (tj % (2 * cj) != 0) return;
+        x[j] = (uint8_t)(tj / (2 * cj));
     }
     for (int i = 0; i < m; ++i) {
         int64_t s = 0;

@@ -24,6 +24,8 @@ from __future__ import annotations
 from dataclasses import dataclass
 from fractions import Fraction
 
+import math
+
 import numpy as np
 
 DEFAULT_N = 1 << 10  # Section 2: N = 2^10 suffices for the market split classes
@@ -38,22 +40,35 @@ class RankDeficient(Exception):
     """Fewer than n - rank(A) + 1 kernel vectors: the rows of A are dependent."""
 
 
-def embedding(A: np.ndarray, d: np.ndarray, N: int = DEFAULT_N) -> list[list[int]]:
-    """Basis vectors (the columns of eq. (2)) for r_max = c_i = 1.
+def bounds_scale(r) -> tuple[int, list[int]]:
+    """r_max = lcm(r_1..r_n) and c_j = r_max / r_j (Section 2, under eq. (2))."""
+    rmax = 1
+    for rj in r:
+        rj = int(rj)
+        if rj < 1:
+            raise ValueError("upper bounds must be >= 1")
+        rmax = rmax * rj // math.gcd(rmax, rj)
+    return rmax, [rmax // int(rj) for rj in r]
 
-    Vector 0 = (-N d_1..-N d_m, -1 (n times), 1); vector j (1..n) =
-    (N a_{1j}..N a_{mj}, 2 e_j, 0).  Each vector has m + n + 1 entries:
+
+def embedding(A: np.ndarray, d: np.ndarray, N: int = DEFAULT_N, r=None) -> list[list[int]]:
+    """Basis vectors (the columns of eq. (2)).
+
+    With upper bounds 0 <= x_j <= r_j (r = None: binary, r_max = c_j = 1):
+    vector 0 = (-N d_1..-N d_m, -r_max (n times), r_max); vector j (1..n) =
+    (N a_{1j}..N a_{mj}, 2 c_j e_j, 0).  Each vector has m + n + 1 entries:
     the m scaled equation rows, the n variable rows, the r_max row last.
     Returned as Python ints (exact).
     """
     A = np.asarray(A)
     m, n = A.shape
+    rmax, c = bounds_scale(r) if r is not None else (1, [1] * n)
     vecs = []
-    v0 = [-N * int(d[i]) for i in range(m)] + [-1] * n + [1]
+    v0 = [-N * int(d[i]) for i in range(m)] + [-rmax] * n + [rmax]
     vecs.append(v0)
     for j in range(n):
         v = [N * int(A[i, j]) for i in range(m)] + [0] * n + [0]
-        v[m + j] = 2
+        v[m + j] = 2 * c[j]
         vecs.append(v)
     return vecs
 
@@ -251,6 +266,9 @@ class Prepared:
     mu: np.ndarray  # float64 (k, k) lower triangle, unit diagonal
     beta: np.ndarray  # float64 (k,)
     bhat: np.ndarray  # float64 (k, n+1)
+    r: np.ndarray | None = None  # upper bounds (None: binary)
+    rmax: int = 1
+    cvec: np.ndarray | None = None  # int64 c_j = r_max / r_j (None: binary)
 
     @property
     def k(self) -> int:
@@ -261,25 +279,28 @@ class Prepared:
         return int(self.basis.shape[1])
 
 
-def prepare_from_basis(A, d, kernel_basis) -> Prepared:
+def prepare_from_basis(A, d, kernel_basis, r=None) -> Prepared:
     """Exact GS of a given kernel basis (k x (n+1) integer rows)."""
     A = np.asarray(A)
     kb = [[int(c) for c in row] for row in np.asarray(kernel_basis).tolist()]
     gs = gram_schmidt_exact(kb)
     m, n = A.shape
+    rmax, c = bounds_scale(r) if r is not None else (1, None)
     return Prepared(m=m, n=n, A=A, d=np.asarray(d), basis=np.array(kb, dtype=np.int64),
-                    gs=gs, mu=gs.mu_f64(), beta=gs.beta_f64(), bhat=gs.bhat_f64())
+                    gs=gs, mu=gs.mu_f64(), beta=gs.beta_f64(), bhat=gs.bhat_f64(),
+                    r=None if r is None else np.asarray(r, dtype=np.int64), rmax=rmax,
+                    cvec=None if c is None else np.asarray(c, dtype=np.int64))
 
 
-def prepare(A, d, N: int = DEFAULT_N, delta: Fraction = Fraction(99, 100)) -> Prepared:
-    """Steps 1-3 of Algorithm 1 in exact arithmetic."""
+def prepare(A, d, N: int = DEFAULT_N, delta: Fraction = Fraction(99, 100), r=None) -> Prepared:
+    """Steps 1-3 of Algorithm 1 in exact arithmetic (r: upper bounds, None = binary)."""
     A = np.asarray(A)
     m, n = A.shape
     if m > n:
         raise ValueError("m must not exceed n")
-    red = lll_exact(embedding(A, d, N), delta)
+    red = lll_exact(embedding(A, d, N, r), delta)
     kern = extract_kernel(red, m)
-    return prepare_from_basis(A, d, kern)
+    return prepare_from_basis(A, d, kern, r)
 
 
 def check_lll_reduced(basis: list[list[int]], delta: Fraction = Fraction(99, 100),
