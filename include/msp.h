@@ -175,6 +175,24 @@ int msp_enumerate(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_
                   const int64_t *basis_dev, int k, int mode, int order, const msp_params *p,
                   uint8_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats, void *stream);
 
+/* Bounded variables (Section 2, eq. (2) in its general form): find x with
+ * A x = d and 0 <= x_j <= r_j (a lower bound l is moved to 0 by the caller:
+ * x := x - l, d := d - A l, r := r - l).  r_dev: int32 n, each 1..255
+ * (MSP_E_ARG otherwise).  The library forms r_max = lcm(r_j) (MSP_E_OVERFLOW
+ * beyond 2^20) and c_j = r_max / r_j; the embedding has -r_max / r_max in
+ * vector 0 and 2 c_j on the diagonal; the enumeration bound is
+ * R = (n+1) r_max^2, the Hoelder test is l > r_max ||w||_1 (1+eps), and a
+ * leaf is a solution when v_n = +-r_max and |v_j| <= r_max (Thm 1), with
+ * x_j = (v_j + r_max) / (2 c_j) written as uint8.  Otherwise as msp_reduce
+ * and msp_enumerate (all r_j = 1 is the binary problem). */
+int msp_reduce_bounded(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                       const int32_t *r_dev, const msp_params *p, int64_t *basis_dev, int *k_out,
+                       void *stream);
+int msp_enumerate_bounded(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                          const int32_t *r_dev, const int64_t *basis_dev, int k, int mode, int order,
+                          const msp_params *p, uint8_t *x_dev, int64_t cap, int64_t *n_found,
+                          msp_stats *stats, void *stream);
+
 /* One instance of a batch: A_dev + A_off holds its m x n matrix, d_dev +
  * d_off its right-hand side, x_dev + x_off its output rows (cap x n). */
 typedef struct {

@@ -42,7 +42,7 @@ MSP_MODEL_NPARAM = 5313
 EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_strerror",
-    "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
+    "msp_reduce_bounded", "msp_enumerate_bounded", "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
     "msp_model_grad", "msp_train_params_default", "msp_model_train",
 )
 
@@ -112,6 +112,11 @@ def _load() -> C.CDLL:
     lib.msp_solve_batch.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params), vp,
                                     C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(Stats), vp]
     lib.msp_solve_batch.restype = i32
+    lib.msp_reduce_bounded.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(Params), vp, C.POINTER(i32), vp]
+    lib.msp_reduce_bounded.restype = i32
+    lib.msp_enumerate_bounded.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, i64,
+                                          C.POINTER(i64), C.POINTER(Stats), vp]
+    lib.msp_enumerate_bounded.restype = i32
     lib.msp_autotune.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params),
                                  C.POINTER(Params), C.POINTER(TunePoint), C.POINTER(i32), vp]
     lib.msp_autotune.restype = i32
@@ -470,3 +475,47 @@ def msp_model_train(ctx: Context, feat: torch.Tensor, label: torch.Tensor, tp: T
     if rc != MSP_OK:
         raise MspError(rc, "msp_model_train")
     return list(losses)[: tp.epochs]
+
+
+# ---- bounded variables ------------------------------------------------------
+
+def msp_reduce_bounded(ctx: Context, A: torch.Tensor, d: torch.Tensor, r: torch.Tensor,
+                       params: Params | None = None) -> torch.Tensor:
+    """Embedding with upper bounds r (int32 device tensor, 1..255) + LLL +
+    kernel extraction; returns the int64 kernel basis (k x (n+1))."""
+    m, n = A.shape
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    rp = _dev_ptr(r, torch.int32, dev, "r")
+    basis = torch.zeros((n + 1, n + 1), dtype=torch.int64, device=dev)
+    k = C.c_int(0)
+    p = params if params is not None else msp_params_default()
+    rc = lib().msp_reduce_bounded(ctx.handle, m, n, ap, dp, rp, C.byref(p), basis.data_ptr(), C.byref(k),
+                                  _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_reduce_bounded")
+    return basis[: k.value].contiguous()
+
+
+def msp_enumerate_bounded(ctx: Context, A: torch.Tensor, d: torch.Tensor, r: torch.Tensor, basis: torch.Tensor, *,
+                          mode: int = MSP_ALL, order: int = MSP_PLAIN, params: Params | None = None,
+                          cap: int = 1 << 16, raise_on_error: bool = True) -> EnumResult:
+    """All (or the first) x with A x = d and 0 <= x <= r on a given kernel basis."""
+    m, n = A.shape
+    k = basis.shape[0]
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    rp = _dev_ptr(r, torch.int32, dev, "r")
+    bp = _dev_ptr(basis, torch.int64, dev, "basis")
+    out = torch.zeros((max(cap, 1), n), dtype=torch.uint8, device=dev)
+    p = params if params is not None else msp_params_default()
+    nf = C.c_int64(0)
+    st = Stats()
+    rc = lib().msp_enumerate_bounded(ctx.handle, m, n, ap, dp, rp, bp, k, int(mode), int(order), C.byref(p),
+                                     out.data_ptr(), int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
+    if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
+        raise MspError(rc, "msp_enumerate_bounded")
+    rows = min(nf.value, cap)
+    return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())

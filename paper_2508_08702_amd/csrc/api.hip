@@ -127,6 +127,7 @@ struct msp_ctx {
     // root orders
     Buf feat, key, key_out, idx_in, sort_tmp;
     Buf left_u, left_meta, top_idx;  // refinement: stage leftovers, best-node indices
+    Buf cvec, rmax;                  // bounded variables: c_j and r_max of the last bounds
     // roots of the last enumeration (for tracing)
     int last_cur = 0, last_L = 0, last_k = 0, last_dim = 0, last_ws = 0, last_m = 0;
     int64_t last_np = 0;
@@ -251,6 +252,8 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->left_u.release();
     c->left_meta.release();
     c->top_idx.release();
+    c->cvec.release();
+    c->rmax.release();
     c->counts.release();
     c->offs.release();
     c->stack.release();
@@ -295,7 +298,8 @@ int msp_gram_schmidt(msp_ctx *c, int k, int dim, const int64_t *basis_dev, doubl
 
 static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
                           const int64_t *basis_dev, int k, int mode, int order, const msp_params *pin, uint8_t *x_dev,
-                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream, int8_t *sol_u = nullptr) {
+                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream, int8_t *sol_u = nullptr,
+                          const int64_t *cvec = nullptr, long long rmax = 1) {
     auto t_call = std::chrono::steady_clock::now();
     if (!c || !A_dev || !d_dev || !basis_dev || !n_found || (cap > 0 && !x_dev) || cap < 0) return MSP_E_ARG;
     if (m < 1 || n < 1 || m > n || n > MSP_MAX_N || k != n - m + 1) return MSP_E_ARG;
@@ -332,7 +336,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     MSP_TRY(hipStreamSynchronize(st));
     if (gs_err) return MSP_E_NUMERIC;
 
-    const double R = (double)(n + 1);  // (n+1) r_max^2, r_max = 1 (Algorithm 1, step 4)
+    const double R = (double)(n + 1) * (double)rmax * (double)rmax;  // (n+1) r_max^2 (Algorithm 1, step 4)
     const double bound = R * (1.0 + p.eps);
     const double hfac = 1.0 + p.eps;
 
@@ -385,6 +389,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             ea.counts = c->counts.as<int64_t>();
             ea.bound = bound;
             ea.hfac = hfac;
+            ea.rmax = (double)rmax;
             ea.hoelder = p.hoelder;
             ea.onedir = p.onedir;
             ea.counters = ctl->counters;
@@ -574,6 +579,9 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.mode = mode;
         wa.bound = bound;
         wa.hfac = hfac;
+        wa.rmax_d = (double)rmax;
+        wa.rmax = rmax;
+        wa.cvec = cvec;
         wa.hoelder = p.hoelder;
         wa.onedir = p.onedir;
         MSP_TRY(hipEventRecord(c->ev[4], st));
@@ -647,7 +655,7 @@ int lll_status(int32_t st) {
 
 // One launch reduces `cnt` instances; descriptors are copied to the device.
 int run_lll(msp_ctx *c, std::vector<LllDesc> &h, const int32_t *A_dev, const int64_t *d_dev, int64_t *out,
-            const msp_params &p, hipStream_t st) {
+            const msp_params &p, hipStream_t st, const int64_t *cvec = nullptr, long long rmax = 1) {
     const int cnt = (int)h.size();
     int maxn = 0;
     size_t work = 0;
@@ -679,6 +687,8 @@ int run_lll(msp_ctx *c, std::vector<LllDesc> &h, const int32_t *A_dev, const int
     la.kout = &dd->kout;
     la.iters = &dd->iters;
     la.stride = (int)(sizeof(LllDesc) / sizeof(int32_t));
+    la.cvec = cvec;
+    la.rmax = rmax;
     MSP_TRY(launch_lll(la, cnt, maxn, st));
     MSP_TRY(hipMemcpyAsync(h.data(), dd, sizeof(LllDesc) * cnt, hipMemcpyDeviceToHost, st));
     MSP_TRY(hipStreamSynchronize(st));
@@ -756,6 +766,57 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
     return first_bad;
 }
 
+
+// r_max and c_j of the bounds r_dev (device), into the context; returns
+// MSP_OK and *rmax_out, or MSP_E_ARG / MSP_E_OVERFLOW.
+static int bounds_setup(msp_ctx *c, int n, const int32_t *r_dev, long long *rmax_out, hipStream_t st) {
+    MSP_TRY(c->cvec.ensure((size_t)n * sizeof(int64_t)));
+    MSP_TRY(c->rmax.ensure(sizeof(long long)));
+    MSP_TRY(launch_bounds_scale(r_dev, n, c->cvec.as<int64_t>(), c->rmax.as<long long>(), st));
+    long long rm = 0;
+    MSP_TRY(hipMemcpyAsync(&rm, c->rmax.p, sizeof(rm), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    if (rm == -1) return MSP_E_ARG;
+    if (rm < 1) return MSP_E_OVERFLOW;
+    *rmax_out = rm;
+    return MSP_OK;
+}
+
+int msp_reduce_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int32_t *r_dev,
+                       const msp_params *pin, int64_t *basis_dev, int *k_out, void *stream) {
+    if (!c || !A_dev || !d_dev || !r_dev || !basis_dev || !k_out) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    *k_out = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    long long rmax = 1;
+    int rc = bounds_setup(c, n, r_dev, &rmax, st);
+    if (rc != MSP_OK) return rc;
+    std::vector<LllDesc> h(1);
+    h[0] = LllDesc{m, n, 0, 0, 0, 0, 0, 0, 0};
+    rc = run_lll(c, h, A_dev, d_dev, basis_dev, p, st, c->cvec.as<int64_t>(), rmax);
+    if (rc != MSP_OK) return rc;
+    c->last_lll_iters = h[0].iters;
+    const int s = lll_status(h[0].status);
+    if (s == MSP_OK) *k_out = h[0].kout;
+    return s;
+}
+
+int msp_enumerate_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int32_t *r_dev,
+                          const int64_t *basis_dev, int k, int mode, int order, const msp_params *p, uint8_t *x_dev,
+                          int64_t cap, int64_t *n_found, msp_stats *stats, void *stream) {
+    if (!c || !r_dev || n < 1 || n > MSP_MAX_N) return MSP_E_ARG;
+    DeviceGuard g(c->device);
+    long long rmax = 1;
+    int rc = bounds_setup(c, n, r_dev, &rmax, (hipStream_t)stream);
+    if (rc != MSP_OK) return rc;
+    return enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, mode, order, p, x_dev, cap, n_found, stats, stream,
+                          nullptr, c->cvec.as<int64_t>(), rmax);
+}
 
 int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,
                  int mode, int order, const msp_params *base, msp_params *best, msp_tune_point *points, int *npoints,

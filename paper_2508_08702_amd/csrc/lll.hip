@@ -59,16 +59,19 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     const int64_t *d = a.d + d_off;
     const long long N = a.N;
 
-    // ---- eq. (2): vector 0 = (-N d; -1 x n; 1), vector j = (N a_j; 2 e_j; 0)
+    // ---- eq. (2): vector 0 = (-N d; -r_max x n; r_max), vector j = (N a_j; 2 c_j e_j; 0)
+    // (binary variables: r_max = c_j = 1)
+    const long long rm = a.cvec ? a.rmax : 1;
     for (int r = 0; r < nv; ++r) {
         for (int q = 0; q < kMaxCols; ++q) {
             const int c = lane + q * kLanes;
             if (c >= len) continue;
             long long v;
             if (r == 0)
-                v = c < m ? -N * (long long)d[c] : (c < m + n ? -1 : 1);
+                v = c < m ? -N * (long long)d[c] : (c < m + n ? -rm : rm);
             else
-                v = c < m ? N * (long long)A[(size_t)c * n + (r - 1)] : (c == m + (r - 1) ? 2 : 0);
+                v = c < m ? N * (long long)A[(size_t)c * n + (r - 1)]
+                          : (c == m + (r - 1) ? 2 * (a.cvec ? (long long)a.cvec[r - 1] : 1) : 0);
             B[(size_t)r * len + c] = v;
         }
     }
@@ -280,6 +283,35 @@ hipError_t launch_lll(const LllArgs &a, int ninst, int max_n, hipStream_t st) {
     hipError_t e = hipFuncSetAttribute((const void *)lll_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(lll_kernel, dim3(ninst), dim3(kLanes), lds, st, a);
+    return hipGetLastError();
+}
+
+__global__ void bounds_scale_kernel(const int32_t *r, int n, int64_t *cvec, long long *rmax) {
+    if (threadIdx.x != 0) return;
+    long long l = 1;
+    bool bad = false;
+    for (int j = 0; j < n && !bad; ++j) {
+        const long long v = r[j];
+        if (v < 1 || v > 255) {
+            *rmax = -1;
+            return;
+        }
+        long long g = l, h = v;
+        while (h) {
+            const long long t = g % h;
+            g = h;
+            h = t;
+        }
+        l = l / g * v;
+        if (l > (1ll << 20)) bad = true;
+    }
+    if (!bad)
+        for (int j = 0; j < n; ++j) cvec[j] = l / r[j];
+    *rmax = bad ? -2 : l;
+}
+
+hipError_t launch_bounds_scale(const int32_t *r, int n, int64_t *cvec, long long *rmax, hipStream_t st) {
+    hipLaunchKernelGGL(bounds_scale_kernel, dim3(1), dim3(64), 0, st, r, n, cvec, rmax);
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ struct ExpandArgs {
     Frontier ch;                   // children (write pass only)
     const int64_t *offs;           // write pass: first child slot per parent
     int64_t *counts;               // count pass: children per parent
-    double bound, hfac;
+    double bound, hfac;            // l2 bound R (1 + eps); Hoelder: l > (rmax h) hfac
+    double rmax;                   // r_max (1 for binary variables)
     int hoelder, onedir;
     unsigned long long *counters;  // [0] evals [1] nodes [2] expansions (write pass)
     int *flags;                    // [1] |u| > 127 seen
@@ -106,7 +107,10 @@ struct WalkArgs {
     unsigned long long *t_start;   // wall clock when the kernel started
     unsigned long long deadline;   // time cap in wall-clock ticks from kernel start (0 = none)
     int mode;                      // 0 all, 1 first
-    double bound, hfac;
+    double bound, hfac;            // l2 bound R (1 + eps); Hoelder: l > (rmax h) hfac
+    double rmax_d;                 // r_max as a double
+    long long rmax;                // r_max: a solution has v_n = +-r_max, |v_j| <= r_max
+    const int64_t *cvec;           // c_j = r_max / r_j (nullptr: binary, c_j = 1)
     int hoelder, onedir;
 };
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);
@@ -193,12 +197,17 @@ struct LllArgs {
     const int64_t *work_off;
     int64_t *out;                  // kernel basis of instance i at out + out_off[i] (k x (n+1))
     const int64_t *out_off;
+    const int64_t *cvec;           // bounded variables: c_j = r_max / r_j (nullptr: binary)
+    long long rmax;                // r_max (1 when cvec is nullptr)
     int32_t *status;               // 0, -2 (rank), -3 (not isolated), -4 (overflow), -10 (no convergence)
     int32_t *kout;                 // zero-top vectors found
     long long *iters;              // LLL iterations used
     int stride;                    // distance between instances, in 4-byte units
 };
 hipError_t launch_lll(const LllArgs &a, int ninst, int max_n, hipStream_t st);
+// r_max = lcm(r_0..r_{n-1}) and c_j = r_max / r_j; *rmax = -1 when some
+// r_j is outside 1..255, -2 when r_max would exceed 2^20
+hipError_t launch_bounds_scale(const int32_t *r, int n, int64_t *cvec, long long *rmax, hipStream_t st);
 size_t lll_lds_bytes(int n);
 
 }  // namespace msp

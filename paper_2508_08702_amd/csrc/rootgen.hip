@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
             if (a.hoelder) {
                 double h = 0.0;
                 for (int j = 0; j < dim; ++j) h += fabs(fma(x, bt[j], wp[j]));
-                fail = l > h * a.hfac;
+                fail = l > (a.rmax * h) * a.hfac;
             }
             if (fail) {
                 if (a.onedir) {

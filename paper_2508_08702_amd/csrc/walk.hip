@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     double *stk = a.stack + walker * (int64_t)k * 4;
     int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    const double bound = a.bound, hfac = a.hfac;
+    const double bound = a.bound, hfac = a.hfac, rmax_d = a.rmax_d;
     const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
 
     double w[DIMP];
@@ -233,21 +233,28 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         // exact leaf test (Thm 1) and A x = d, integers only
         if (__ballot(leafpend != 0)) {
             if (leafpend && state == RUN) {
+                // v = sum_i u_i b_i exactly.  A solution has v_n = +-r_max and,
+                // with that sign taken off, |v_j| <= r_max (Thm 1); then
+                // x_j = (v_j + r_max) / (2 c_j), and A x = d is checked.
+                const int64_t rmax = a.rmax;
                 bool ok = true;
                 int64_t vn = (int64_t)u * a.basis[a.n];
                 for (int i = 1; i < k; ++i) vn += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + a.n];
-                if (vn != 1 && vn != -1) ok = false;
+                if (vn != rmax && vn != -rmax) ok = false;
+                const int64_t sg = vn > 0 ? 1 : -1;
                 for (int mi = 0; mi < a.m && ok; ++mi) {
                     int64_t acc = 0;
                     for (int j = 0; j < a.n; ++j) {
                         int64_t sv = (int64_t)u * a.basis[j];
                         for (int i = 1; i < k; ++i) sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                        sv *= vn;
-                        if (sv != 1 && sv != -1) {
+                        sv *= sg;
+                        const int64_t cj2 = 2 * (a.cvec ? a.cvec[j] : 1);
+                        const int64_t tj = sv + rmax;
+                        if (sv > rmax || sv < -rmax || tj % cj2 != 0) {
                             ok = false;
                             break;
                         }
-                        if (sv == 1) acc += a.A[(size_t)mi * a.n + j];
+                        acc += (int64_t)a.A[(size_t)mi * a.n + j] * (tj / cj2);
                     }
                     if (ok && acc != a.d[mi]) ok = false;
                 }
@@ -264,7 +271,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                             int64_t sv = (int64_t)u * a.basis[j];
                             for (int i = 1; i < k; ++i)
                                 sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                            xo[j] = (uint8_t)((sv * vn + 1) / 2);
+                            xo[j] = (uint8_t)((sv * sg + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
                         }
                     }
                     if (a.mode == 1) {
@@ -511,7 +518,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
 
             // ---- Hoelder test and the step that follows ----
             if (kind == K_NODE) {
-                const bool fail = hoelder && (lcur > h * hfac);
+                const bool fail = hoelder && (lcur > (rmax_d * h) * hfac);
                 if (fail) {
                     if (!onedir_cut) {
                         advance();
