@@ -1,0 +1,50 @@
+"""Full-size parity: the exhaustive GPU walk of a planted m=9, n=80, D=200
+instance (seed 4508, the benchmark's instance) on the oracle's exact-LLL
+basis against the stored oracle result (tests/golden/m9_seed4508.json, written
+by tests/golden/make_m9_golden.py from oracle/ alone: about 1.9e11 nodes,
+an hour of CPU): the same solution set and the same search counters."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import msp_instances as mi
+from oracle import enum as E
+from oracle import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m9_seed4508.json")
+
+
+def test_m9_exhaustive_matches_stored_oracle_run():
+    import hashlib
+
+    import paper_2508_08702_amd as M
+    g = json.load(open(GOLDEN))
+    inst = mi.msp_class(9, g["instance"]["D"], g["instance"]["seed"])
+    P = L.prepare(inst.A, inst.d)
+    digest = hashlib.sha256(np.ascontiguousarray(P.basis, dtype=np.int64).tobytes()).hexdigest()
+    assert digest == g["basis_sha256"]
+    ctx = M.Context(0)
+    try:
+        dev = torch.device("cuda", 0)
+        A = torch.from_numpy(inst.A).to(dev)
+        d = torch.from_numpy(inst.d).to(dev)
+        Bk = torch.from_numpy(np.ascontiguousarray(P.basis)).to(dev)
+        print("  gpu exhaustive m=9 seed 4508 on the oracle basis", flush=True)
+        r = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(time_cap_ms=110000.0))
+        torch.cuda.synchronize()
+        assert r.status == M.MSP_OK
+        x = E.sort_rows(r.x.cpu().numpy())
+        want = E.sort_rows(np.array(g["solutions"], dtype=np.uint8))
+        assert r.n_found == g["n_found"] and np.array_equal(x, want)
+        for key in ("evals", "nodes", "expansions", "leaves"):
+            assert r.stats[key] == g[key], key
+        assert any(np.array_equal(row, inst.x_planted) for row in x)
+    finally:
+        ctx.close()
