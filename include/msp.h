@@ -93,7 +93,7 @@ typedef struct {
     int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
     double time_cap_ms;   /* enumeration wall-time cap; <= 0 = none             [0] */
     int refine;           /* MSP_FIRST with a non-plain order: refinement stages
-                           * (see msp_enumerate); -1 = auto (up to 64), 0 = off [-1] */
+                           * (see msp_enumerate); -1 = up to 64, 0 = off          [0] */
     int refine_keep;      /* best nodes expanded further per stage; 0 = auto
                            * (256 per CU)                                        [0] */
 } msp_params;

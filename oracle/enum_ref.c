@@ -80,6 +80,9 @@ typedef struct {
     int *timed_out;
     const int64_t *cvec;    /* n, c_j = r_max / r_j for bounded variables;
                              * NULL: binary (r_max = c_j = 1)                 */
+    int disc_budget;        /* limited discrepancy search: at most this many
+                             * levels on a path take a value other than their
+                             * first zig-zag value; < 0: no limit             */
 } orc_args;
 
 /* Subtree roots, stored flat: root r has prefix u[r*k + i] (i >= level),
@@ -89,6 +92,7 @@ typedef struct {
     double *w;
     double *l;
     int *topzero;
+    int *dsc;               /* discrepancies on the root's prefix            */
     int64_t n, cap;
 } orc_roots;
 
@@ -152,7 +156,7 @@ static void leaf(orc_walker *W) {
 }
 
 static void roots_free(orc_roots *R) {
-    free(R->u); free(R->w); free(R->l); free(R->topzero);
+    free(R->u); free(R->w); free(R->l); free(R->topzero); free(R->dsc);
     memset(R, 0, sizeof(*R));
 }
 
@@ -166,12 +170,14 @@ static int roots_grow(orc_roots *R, int k, int dim) {
     if (nl) R->l = nl;
     int *nz = (int *)realloc(R->topzero, (size_t)nc * sizeof(int));
     if (nz) R->topzero = nz;
-    if (!nu || !nw || !nl || !nz) return -1;
+    int *nd = (int *)realloc(R->dsc, (size_t)nc * sizeof(int));
+    if (nd) R->dsc = nd;
+    if (!nu || !nw || !nl || !nz || !nd) return -1;
     R->cap = nc;
     return 0;
 }
 
-static void push_root(orc_walker *W, const double *w, double l, int topzero) {
+static void push_root(orc_walker *W, const double *w, double l, int topzero, int dsc) {
     const int k = W->a->k, dim = W->a->dim;
     orc_roots *R = &W->roots;
     if (R->n == R->cap && roots_grow(R, k, dim) != 0) { W->oom = 1; g_sh->stop = 1; return; }
@@ -180,6 +186,7 @@ static void push_root(orc_walker *W, const double *w, double l, int topzero) {
     memcpy(R->w + r * dim, w, sizeof(double) * (size_t)dim);
     R->l[r] = l;
     R->topzero[r] = topzero;
+    R->dsc[r] = dsc;
 }
 
 static void check_time(orc_walker *W) {
@@ -210,7 +217,11 @@ static double centre(const orc_args *a, const int *u, int t) {
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, int topzero) {
+/* dsc: discrepancies on the path above level t (Section 3, limited
+ * discrepancy search): a level whose value is not its first zig-zag value u1
+ * counts one.  With a budget, a level stops at the first value that would
+ * exceed it -- every later value of the level is a discrepancy as well. */
+static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, int topzero, int dsc) {
     const orc_args *a = W->a;
     const int dim = a->dim;
     double w[ORC_MAXDIM];
@@ -228,6 +239,7 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
     int u = u1;
     for (;;) {
         if (g_sh->stop) { W->u[t] = 0; return; }
+        if (a->disc_budget >= 0 && u != u1 && dsc >= a->disc_budget) break;
         const double x = (double)u + y;
         const double l = x * x * a->beta[t] + lpar;
         W->cnt[0]++;
@@ -258,9 +270,9 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
             W->cnt[2]++;
             if (W->lvl) W->lvl[t * 3 + 2]++;
             if (W->collect_level == t) {
-                push_root(W, w, l, topzero && u == 0);
+                push_root(W, w, l, topzero && u == 0, dsc + (u != u1));
             } else {
-                enum_level(W, t - 1, w, l, topzero && u == 0);
+                enum_level(W, t - 1, w, l, topzero && u == 0, dsc + (u != u1));
             }
         } else {
             W->cnt[3]++;
@@ -288,7 +300,7 @@ static void *worker(void *arg) {
         if (i >= R->n) break;
         memset(W->u, 0, sizeof(W->u));
         for (int j = L; j < a->k; ++j) W->u[j] = R->u[i * a->k + j];
-        enum_level(W, L - 1, R->w + i * a->dim, R->l[i], R->topzero[i]);
+        enum_level(W, L - 1, R->w + i * a->dim, R->l[i], R->topzero[i], R->dsc[i]);
         check_time(W);
     }
     pthread_mutex_lock(&g_sh->lock);
@@ -331,10 +343,11 @@ int orc_enumerate(orc_args *a) {
         memset(gen.roots.w, 0, sizeof(double) * (size_t)a->dim);
         gen.roots.l[0] = 0.0;
         gen.roots.topzero[0] = 1;
+        gen.roots.dsc[0] = 0;
         gen.roots.n = 1;
     } else {
         gen.collect_level = a->k - a->split;
-        enum_level(&gen, a->k - 1, w0, 0.0, 1);
+        enum_level(&gen, a->k - 1, w0, 0.0, 1, 0);
         if (gen.oom) { roots_free(&gen.roots); free(gen.lvl); return -2; }
     }
     for (int c = 0; c < 4; ++c) sh.cnt[c] += gen.cnt[c];

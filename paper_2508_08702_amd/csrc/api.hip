@@ -186,7 +186,7 @@ int msp_params_default(msp_params *p) {
     p->hoelder = 1;
     p->onedir = 1;
     p->time_cap_ms = 0.0;
-    p->refine = -1;
+    p->refine = 0;
     p->refine_keep = 0;
     return MSP_OK;
 }

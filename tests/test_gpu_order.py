@@ -200,7 +200,7 @@ def test_refined_first_search_stays_exhaustive(M, ctx, order, m, seed, feasible)
     base = M.msp_params_default(time_cap_ms=60000.0)
     plain = M.msp_enumerate(ctx, A, d, Bk, params=base)
     assert plain.status == M.MSP_OK and plain.n_found == ref.n_found
-    prm = M.msp_params_default(time_cap_ms=60000.0, target_roots=2048, refine_keep=64)
+    prm = M.msp_params_default(time_cap_ms=60000.0, target_roots=2048, refine=-1, refine_keep=64)
     print(f"  refined first m={m} seed={seed} order={order} oracle solutions={ref.n_found}", flush=True)
     r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=M.MSP_FIRST, order=order, cap=64)
     assert r.status == M.MSP_OK
