@@ -134,9 +134,13 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
     if args.ttfs_seeds:
         keep = {int(x) for x in args.ttfs_seeds.split(",")}
         insts = [i for i in insts if i.seed in keep]
-    orders = {"plain": M.MSP_PLAIN, "learned": M.MSP_LEARNED, "discrepancy": M.MSP_DISCREPANCY}
+    # name: (mode, root order): one first-solution walk in an order, or
+    # limited discrepancy search (passes with a rising budget) in an order
+    orders = {"plain": (M.MSP_FIRST, M.MSP_PLAIN), "learned": (M.MSP_FIRST, M.MSP_LEARNED),
+              "discrepancy": (M.MSP_FIRST, M.MSP_DISCREPANCY), "lds": (M.MSP_LDS, M.MSP_PLAIN),
+              "lds-learned": (M.MSP_LDS, M.MSP_LEARNED)}
     names = [o for o in args.orders.split(",") if o]
-    if "learned" in names:
+    if any(o.endswith("learned") for o in names):
         M.msp_model_set(ctx, np.load(args.model))
     per = []
     for inst in insts:
@@ -148,8 +152,8 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             Bk = M.msp_reduce(ctx, A, d, prm)
-            r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=M.MSP_FIRST, order=orders[name], cap=64,
-                                raise_on_error=False)
+            mode, order = orders[name]
+            r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=mode, order=order, cap=64, raise_on_error=False)
             torch.cuda.synchronize()
             e2e = (time.perf_counter() - t0) * 1e3
             xs = r.x.cpu().numpy().astype(np.int64)

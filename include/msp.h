@@ -57,8 +57,12 @@ enum {
 
 #define MSP_MAX_N 127        /* largest n accepted (n + 1 <= 128)                */
 
-/* enumeration modes */
-enum { MSP_ALL = 0, MSP_FIRST = 1 };
+/* enumeration modes: every solution; a first solution by one walk; a first
+ * solution by limited discrepancy search (Section 3): walks that admit at
+ * most B = 0, 1, 2, ... levels whose value is not their first zig-zag value,
+ * then one walk without a budget (exhaustive), stopping at the first pass with
+ * a hit.  msp_stats then sums the passes (stages = passes run). */
+enum { MSP_ALL = 0, MSP_FIRST = 1, MSP_LDS = 2 };
 /* Orders in which the subtree roots are walked.  The order changes only
  * which solutions MSP_FIRST meets first and how soon; MSP_ALL returns the same
  * set and the same search-tree counters in every order.
@@ -96,6 +100,8 @@ typedef struct {
                            * (see msp_enumerate); -1 = up to 64, 0 = off          [0] */
     int refine_keep;      /* best nodes expanded further per stage; 0 = auto
                            * (256 per CU)                                        [0] */
+    int disc_budget;      /* at most this many discrepancies on any walked path
+                           * (Section 3); -1 = no limit, at most 255            [-1] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).

@@ -31,6 +31,7 @@ MSP_E_NUMERIC = -10
 
 MSP_ALL = 0
 MSP_FIRST = 1
+MSP_LDS = 2
 MSP_PLAIN = 0
 MSP_LEARNED = 1
 MSP_DISCREPANCY = 2
@@ -58,7 +59,7 @@ class Params(C.Structure):
         ("N", C.c_int64), ("delta", C.c_double), ("eps", C.c_double),
         ("split_depth", C.c_int), ("block", C.c_int), ("target_roots", C.c_int),
         ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
-        ("refine", C.c_int), ("refine_keep", C.c_int),
+        ("refine", C.c_int), ("refine_keep", C.c_int), ("disc_budget", C.c_int),
     ]
 
 

@@ -71,7 +71,7 @@ struct Buf {
 };
 
 struct FrontierBuf {
-    Buf u, w, l, tz;
+    Buf u, w, l, tz, dsc;
     int64_t cap = 0;
     hipError_t ensure(int64_t n, int k, int ws) {
         hipError_t e;
@@ -79,15 +79,19 @@ struct FrontierBuf {
         if ((e = w.ensure((size_t)n * ws * sizeof(double))) != hipSuccess) return e;
         if ((e = l.ensure((size_t)n * sizeof(double))) != hipSuccess) return e;
         if ((e = tz.ensure((size_t)n)) != hipSuccess) return e;
+        if ((e = dsc.ensure((size_t)n)) != hipSuccess) return e;
         cap = n;
         return hipSuccess;
     }
-    Frontier view() const { return Frontier{u.as<int8_t>(), w.as<double>(), l.as<double>(), tz.as<uint8_t>()}; }
+    Frontier view() const {
+        return Frontier{u.as<int8_t>(), w.as<double>(), l.as<double>(), tz.as<uint8_t>(), dsc.as<uint8_t>()};
+    }
     void release() {
         u.release();
         w.release();
         l.release();
         tz.release();
+        dsc.release();
         cap = 0;
     }
 };
@@ -188,6 +192,7 @@ int msp_params_default(msp_params *p) {
     p->time_cap_ms = 0.0;
     p->refine = 0;
     p->refine_keep = 0;
+    p->disc_budget = -1;
     return MSP_OK;
 }
 
@@ -310,7 +315,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     msp_params_default(&p);
     if (pin) p = *pin;
     if (!(p.eps >= 0.0) || p.split_depth < -1 || p.split_depth > k - 1) return MSP_E_ARG;
-    if (p.refine < -1 || p.refine_keep < 0 || p.target_roots < 0) return MSP_E_ARG;
+    if (p.refine < -1 || p.refine_keep < 0 || p.target_roots < 0 || p.disc_budget > 255) return MSP_E_ARG;
     *n_found = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -390,6 +395,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             ea.bound = bound;
             ea.hfac = hfac;
             ea.rmax = (double)rmax;
+            ea.budget = p.disc_budget;
             ea.hoelder = p.hoelder;
             ea.onedir = p.onedir;
             ea.counters = ctl->counters;
@@ -582,6 +588,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.rmax_d = (double)rmax;
         wa.rmax = rmax;
         wa.cvec = cvec;
+        wa.budget = p.disc_budget;
         wa.hoelder = p.hoelder;
         wa.onedir = p.onedir;
         MSP_TRY(hipEventRecord(c->ev[4], st));
@@ -626,11 +633,80 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     return MSP_OK;
 }
 
+// Limited discrepancy search for a first solution (paper, Section 3): walks
+// with discrepancy budget B = 0, 1, 2, ... (each a first-solution walk that
+// admits at most B levels off their first zig-zag value), then one walk
+// without a budget, which is exhaustive.  Stops at the first pass with a
+// hit; counters and times are summed over the passes (stages = passes run).
+static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
+                      int k, int order, const msp_params *pin, uint8_t *x_dev, int64_t cap, int64_t *n_found,
+                      msp_stats *stats, void *stream, const int64_t *cvec, long long rmax) {
+    auto t0 = std::chrono::steady_clock::now();
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (!n_found) return MSP_E_ARG;
+    msp_stats acc;
+    std::memset(&acc, 0, sizeof(acc));
+    acc.ttfs_ms = -1.0;
+    int rc = MSP_OK, passes = 0;
+    const int maxb = std::min(k, 255);
+    for (int B = 0; B <= maxb + 1; ++B) {
+        msp_params q = p;
+        q.disc_budget = B <= maxb ? B : -1;
+        if (p.time_cap_ms > 0) {
+            const double used =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (used >= p.time_cap_ms) {
+                rc = MSP_E_TIMEOUT;
+                break;
+            }
+            q.time_cap_ms = p.time_cap_ms - used;
+        }
+        msp_stats st;
+        std::memset(&st, 0, sizeof(st));
+        const double before =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        rc = enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, MSP_FIRST, order, &q, x_dev, cap, n_found, &st,
+                            stream, nullptr, cvec, rmax);
+        ++passes;
+        acc.evals += st.evals;
+        acc.nodes += st.nodes;
+        acc.expansions += st.expansions;
+        acc.leaves += st.leaves;
+        acc.items += st.items;
+        acc.roots = st.roots;
+        acc.split_depth = st.split_depth;
+        acc.k = st.k;
+        acc.block = st.block;
+        acc.root_level = st.root_level;
+        acc.initial_items = st.initial_items;
+        acc.gs_ms += st.gs_ms;
+        acc.rootgen_ms += st.rootgen_ms;
+        acc.ordering_ms += st.ordering_ms;
+        acc.kernel_ms += st.kernel_ms;
+        if (rc != MSP_OK) break;
+        if (*n_found > 0) {
+            // host time of the earlier passes, then this pass up to its hit
+            acc.ttfs_ms = before + (st.ttfs_ms >= 0.0 ? st.ttfs_ms + st.gs_ms + st.rootgen_ms : st.total_ms);
+            break;
+        }
+        if (B > maxb) break;  // the unlimited walk found nothing: no solution
+    }
+    acc.stages = passes;
+    acc.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = acc;
+    return rc;
+}
+
 extern "C" {
 
 int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
                   int k, int mode, int order, const msp_params *p, uint8_t *x_dev, int64_t cap, int64_t *n_found,
                   msp_stats *stats, void *stream) {
+    if (mode == MSP_LDS)
+        return lds_search(c, m, n, A_dev, d_dev, basis_dev, k, order, p, x_dev, cap, n_found, stats, stream, nullptr,
+                          1);
     return enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, mode, order, p, x_dev, cap, n_found, stats, stream);
 }
 
@@ -755,7 +831,10 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
         int s = lll_status(h[i].status);
         msp_stats sti;
         std::memset(&sti, 0, sizeof(sti));
-        if (s == MSP_OK)
+        if (s == MSP_OK && mode == MSP_LDS)
+            s = lds_search(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off, h[i].kout, order, &p,
+                           x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream, nullptr, 1);
+        else if (s == MSP_OK)
             s = enumerate_impl(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off, h[i].kout, mode,
                                order, &p, x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream);
         sti.reduce_ms = reduce_ms;
@@ -814,6 +893,9 @@ int msp_enumerate_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     long long rmax = 1;
     int rc = bounds_setup(c, n, r_dev, &rmax, (hipStream_t)stream);
     if (rc != MSP_OK) return rc;
+    if (mode == MSP_LDS)
+        return lds_search(c, m, n, A_dev, d_dev, basis_dev, k, order, p, x_dev, cap, n_found, stats, stream,
+                          c->cvec.as<int64_t>(), rmax);
     return enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, mode, order, p, x_dev, cap, n_found, stats, stream,
                           nullptr, c->cvec.as<int64_t>(), rmax);
 }

@@ -16,11 +16,15 @@ namespace msp {
 //                         w[r .. r+DIMP) without wrapping)
 //   l   f64   [cap]       ||w||^2 by the partial-norm recurrence
 //   tz  uint8 [cap]       1 while every u above the record's level is zero
+//   dsc uint8 [cap]       discrepancies on the prefix (levels whose value is
+//                         not their first zig-zag value; limited discrepancy
+//                         search, paper Section 3)
 struct Frontier {
     int8_t *u;
     double *w;
     double *l;
     uint8_t *tz;
+    uint8_t *dsc;
 };
 
 // Width of the padded projected vector held per lane, and of records.
@@ -55,6 +59,7 @@ struct ExpandArgs {
     int64_t *counts;               // count pass: children per parent
     double bound, hfac;            // l2 bound R (1 + eps); Hoelder: l > (rmax h) hfac
     double rmax;                   // r_max (1 for binary variables)
+    int budget;                    // discrepancy budget (< 0: none)
     int hoelder, onedir;
     unsigned long long *counters;  // [0] evals [1] nodes [2] expansions (write pass)
     int *flags;                    // [1] |u| > 127 seen
@@ -69,7 +74,8 @@ hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t 
 // zig-zag continuation at level T).
 //   u     int8 [cap x k]  prefix (natural level index; entries <= T are 0)
 //   meta  int4 [cap]      {T, u_start, flags (onedir 1, dir>0 2, topzero 4,
-//                          fresh 8: start the level from its first value), 0}
+//                          fresh 8: start the level from its first value),
+//                          discrepancies on the prefix above level T}
 //   ready int  [cap]      set (release) once a donated item is fully written
 struct Pool {
     int8_t *u;
@@ -111,6 +117,7 @@ struct WalkArgs {
     double rmax_d;                 // r_max as a double
     long long rmax;                // r_max: a solution has v_n = +-r_max, |v_j| <= r_max
     const int64_t *cvec;           // c_j = r_max / r_j (nullptr: binary, c_j = 1)
+    int budget;                    // discrepancy budget (< 0: none)
     int hoelder, onedir;
 };
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);

@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         const double *wp = a.par.w + p * ws;
         const double lpar = a.par.l[p];
         const bool tz = a.par.tz[p] != 0;
+        const int pd = a.par.dsc[p];
         const double y = centre_natural(up, a.mu, k, t);
         const Zig z = zig_init(y, tz);
         int u = z.u1;
@@ -35,6 +36,8 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         int64_t slot = WRITE ? a.offs[p] : 0;
         int64_t nch = 0;
         for (;;) {
+            // a budget stops the level at the first value that would exceed it
+            if (a.budget >= 0 && u != z.u1 && pd >= a.budget) break;
             const double x = add_rn((double)u, y);
             const double l = partial_norm(x, beta, lpar);
             ++ce;
@@ -65,6 +68,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
                     for (int j = a.dimp; j < ws; ++j) wc[j] = wc[j - a.dimp];
                     a.ch.l[slot] = l;
                     a.ch.tz[slot] = (tz && u == 0) ? 1 : 0;
+                    a.ch.dsc[slot] = (uint8_t)(pd + (u != z.u1 ? 1 : 0));
                     ++slot;
                 }
                 ++nch;
@@ -94,6 +98,7 @@ __global__ void frontier_init_kernel(Frontier f, int k, int ws) {
     if (threadIdx.x == 0) {
         f.l[0] = 0.0;
         f.tz[0] = 1;
+        f.dsc[0] = 0;
     }
 }
 
@@ -130,7 +135,7 @@ __global__ void pool_init_kernel(Frontier f, int64_t nroots, int k, int L, Pool 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nroots) {
         for (int j = 0; j < k; ++j) pool.u[i * k + j] = j >= L ? f.u[i * k + j] : (int8_t)0;
-        pool.meta[i] = make_int4(L - 1, 0, 8 | (f.tz[i] ? 4 : 0), 0);
+        pool.meta[i] = make_int4(L - 1, 0, 8 | (f.tz[i] ? 4 : 0), f.dsc[i]);
         pool.ready[i] = 1;
     }
     for (int64_t j = nroots + i; j < pool.cap; j += (int64_t)gridDim.x * blockDim.x) pool.ready[j] = 0;
@@ -147,6 +152,7 @@ __global__ void gather_frontier_kernel(Frontier src, const int64_t *idx, int64_t
     if (lane == 0) {
         dst.l[r] = src.l[s];
         dst.tz[r] = src.tz[s];
+        dst.dsc[r] = src.dsc[s];
     }
 }
 
@@ -158,7 +164,7 @@ __global__ void frontier_items_kernel(Frontier src, const int64_t *idx, int64_t 
     if (r >= n) return;
     const int64_t s = idx[r];
     for (int j = 0; j < k; ++j) iu[r * k + j] = j >= L ? src.u[s * k + j] : (int8_t)0;
-    imeta[r] = make_int4(L - 1, 0, 8 | (src.tz[s] ? 4 : 0), 0);
+    imeta[r] = make_int4(L - 1, 0, 8 | (src.tz[s] ? 4 : 0), src.dsc[s]);
 }
 
 __global__ void fill_int_kernel(int *p, int64_t n, int v) {

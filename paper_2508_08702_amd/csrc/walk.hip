@@ -190,6 +190,9 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     double y = 0.0, lpar = 0.0, lcur = 0.0, bt = 1.0;
     double Py = 0.0, Pl = 0.0, Pbt = 1.0;  // cached state of level t+1
     int Pu = 0, Pf = 0, Pdirty = 0;  // Pdirty: cache differs from stack entry t+1
+    // discrepancies on the path above level t, and above level t+1 (Pdsc)
+    int dsc = 0, Pdsc = 0;
+    const int budget = a.budget;
     unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;
     unsigned long long t_end = 0;
     if (lane == 0) {
@@ -296,28 +299,34 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             }
             if (__shfl(want, 0, 64)) {
                 bool cand = state == RUN && top > t && top >= k / 6;
-                int D = top, un = 0, fD = 0;
+                int D = top, un = 0, fD = 0, dD = 0;
                 if (cand) {
                     double yD, lD, bD;
                     int uD;
                     if (D == t + 1) {
-                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf;
+                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf; dD = Pdsc;
                     } else {
                         const double *e = stk + (size_t)D * 4;
-                        yD = e[0]; lD = e[1]; fD = (int)e[2];
+                        yD = e[0]; lD = e[1]; fD = (int)e[2]; dD = (int)e[3];
                         bD = s_beta[D];
                         uD = my_u[k - 1 - D];
                     }
                     const int odD = fD & F_ONEDIR, drD = (fD & F_DIRPOS) ? 1 : -1;
                     const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
                     un = odD ? uD + drD : zig_next(zD, uD);
-                    const double l = partial_norm(add_rn((double)un, yD), bD, lD);
-                    if (!(l <= bound)) {
-                        // nothing untried left at level D: this is the failing
-                        // evaluation that would end level D, so count it here
-                        ++c_eval;
+                    if (budget >= 0 && un != zD.u1 && dD >= budget) {
+                        // the budget ends level D before its next value
                         top = D - 1;
                         cand = false;
+                    } else {
+                        const double l = partial_norm(add_rn((double)un, yD), bD, lD);
+                        if (!(l <= bound)) {
+                            // nothing untried left at level D: this is the failing
+                            // evaluation that would end level D, so count it here
+                            ++c_eval;
+                            top = D - 1;
+                            cand = false;
+                        }
                     }
                 }
                 const unsigned long long dm = __ballot(cand);
@@ -339,7 +348,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         const int64_t slot = (int64_t)base + rank;
                         int8_t *pu = a.pool.u + slot * k;
                         for (int j = 0; j < k; ++j) pu[j] = j > D ? my_u[k - 1 - j] : (int8_t)0;
-                        a.pool.meta[slot] = make_int4(D, un, fD & (F_ONEDIR | F_DIRPOS | F_TZ), 0);
+                        a.pool.meta[slot] = make_int4(D, un, fD & (F_ONEDIR | F_DIRPOS | F_TZ), dD);
                         __hip_atomic_store(&a.pool.ready[slot], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         top = D - 1;
                     }
@@ -410,6 +419,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 t = T;
                 top = T;
                 tz = (mt.z & F_TZ) ? 1 : 0;
+                dsc = mt.w;
                 bt = s_beta[T];
                 enter_level();
                 if (!(mt.z & F_FRESH)) {
@@ -436,6 +446,8 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             double coef = 0.0;
             bool popped = false;
             while (state == RUN) {
+                // a discrepancy budget ends the level at the first value beyond it
+                if (!fex && budget >= 0 && u != z.u1 && dsc >= budget) fex = 1;
                 if (!fex) {
                     const double x = add_rn((double)u, y);
                     const double l = partial_norm(x, bt, lpar);
@@ -480,6 +492,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 lpar = Pl;
                 bt = Pbt;
                 u = Pu;
+                dsc = Pdsc;
                 onedir = Pf & F_ONEDIR;
                 dir = (Pf & F_DIRPOS) ? 1 : -1;
                 tz = (Pf & F_TZ) ? 1 : 0;
@@ -491,6 +504,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     Py = e[0];
                     Pl = e[1];
                     Pf = (int)e[2];
+                    Pdsc = (int)e[3];
                     Pbt = s_beta[t + 1];
                     Pu = my_u[k - 2 - t];
                     Pdirty = 0;
@@ -541,8 +555,11 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                             e[0] = Py;
                             e[1] = Pl;
                             e[2] = (double)Pf;
+                            e[3] = (double)Pdsc;
                         }
                         Pdirty = 1;
+                        Pdsc = dsc;
+                        dsc += (u != z.u1) ? 1 : 0;
                         Py = y;
                         Pl = lpar;
                         Pbt = bt;
