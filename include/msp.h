@@ -102,6 +102,9 @@ typedef struct {
                            * (256 per CU)                                        [0] */
     int disc_budget;      /* at most this many discrepancies on any walked path
                            * (Section 3); -1 = no limit, at most 255            [-1] */
+    int bkz_block;        /* msp_reduce: BKZ block size applied to the kernel
+                           * basis after LLL (Section 2); 0 = LLL only, else 2..40 [0] */
+    int bkz_tours;        /* BKZ tour limit                                      [8] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).
@@ -139,6 +142,10 @@ int msp_ctx_create(int device, msp_ctx **out);
 void msp_ctx_destroy(msp_ctx *ctx);
 
 /* Steps 1-2 of Algorithm 1 on the GPU (Section 2, eq. (2)).
+ * With p->bkz_block >= 2 the extracted kernel basis is further BKZ-reduced
+ * with that block size (exact unimodular integer updates; the solution set
+ * does not change, the enumeration tree usually shrinks); if an entry would
+ * exceed 2^26 the LLL basis is returned instead.
  * Builds the embedding basis with scale p->N, LLL-reduces it in FP64 with
  * exact int64 basis updates (Lovász p->delta), keeps the reduced vectors whose
  * first m entries are zero and writes them, top entries dropped, to

@@ -60,6 +60,7 @@ class Params(C.Structure):
         ("split_depth", C.c_int), ("block", C.c_int), ("target_roots", C.c_int),
         ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
         ("refine", C.c_int), ("refine_keep", C.c_int), ("disc_budget", C.c_int),
+        ("bkz_block", C.c_int), ("bkz_tours", C.c_int),
     ]
 
 

@@ -132,6 +132,7 @@ struct msp_ctx {
     Buf feat, key, key_out, idx_in, sort_tmp;
     Buf left_u, left_meta, top_idx;  // refinement: stage leftovers, best-node indices
     Buf cvec, rmax;                  // bounded variables: c_j and r_max of the last bounds
+    Buf bkz_out, bkz_save;           // BKZ status words and the LLL basis kept for a fallback
     // roots of the last enumeration (for tracing)
     int last_cur = 0, last_L = 0, last_k = 0, last_dim = 0, last_ws = 0, last_m = 0;
     int64_t last_np = 0;
@@ -193,6 +194,8 @@ int msp_params_default(msp_params *p) {
     p->refine = 0;
     p->refine_keep = 0;
     p->disc_budget = -1;
+    p->bkz_block = 0;
+    p->bkz_tours = 8;
     return MSP_OK;
 }
 
@@ -259,6 +262,8 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->top_idx.release();
     c->cvec.release();
     c->rmax.release();
+    c->bkz_out.release();
+    c->bkz_save.release();
     c->counts.release();
     c->offs.release();
     c->stack.release();
@@ -772,6 +777,37 @@ int run_lll(msp_ctx *c, std::vector<LllDesc> &h, const int32_t *A_dev, const int
 }
 }  // namespace
 
+// BKZ of an extracted kernel basis in place (k x dim); keeps the LLL basis
+// when an entry would outgrow the exact Gram.
+static int bkz_after_lll(msp_ctx *c, const msp_params &p, int64_t *basis_dev, int k, int dim, hipStream_t st) {
+    if (p.bkz_block < 2 || k < 2) return MSP_OK;
+    if (bkz_lds_bytes(k) > 160 * 1024) return MSP_E_UNSUPPORTED;
+    const size_t nb = (size_t)k * dim * sizeof(int64_t);
+    MSP_TRY(c->bkz_save.ensure(nb));
+    MSP_TRY(c->bkz_out.ensure(64));
+    MSP_TRY(hipMemcpyAsync(c->bkz_save.p, basis_dev, nb, hipMemcpyDeviceToDevice, st));
+    BkzArgs b{};
+    b.k = k;
+    b.dim = dim;
+    b.B = basis_dev;
+    b.beta = p.bkz_block;
+    b.tours = p.bkz_tours > 0 ? p.bkz_tours : 1;
+    b.delta = p.delta;
+    b.max_nodes = 1ll << 18;
+    b.max_lll_iters = 1ll << 16;
+    b.out = c->bkz_out.as<int>();
+    b.nodes = reinterpret_cast<long long *>(c->bkz_out.as<int>() + 4);
+    MSP_TRY(launch_bkz(b, st));
+    int out[2] = {0, 0};
+    MSP_TRY(hipMemcpyAsync(out, b.out, sizeof(out), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    if (out[0] == -4) {  // entries too large for the exact Gram: keep the LLL basis
+        MSP_TRY(hipMemcpyAsync(basis_dev, c->bkz_save.p, nb, hipMemcpyDeviceToDevice, st));
+        MSP_TRY(hipStreamSynchronize(st));
+    }
+    return MSP_OK;
+}
+
 int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *pin,
                int64_t *basis_dev, int *k_out, void *stream) {
     if (!c || !A_dev || !d_dev || !basis_dev || !k_out) return MSP_E_ARG;
@@ -780,6 +816,7 @@ int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_
     msp_params_default(&p);
     if (pin) p = *pin;
     if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    if (p.bkz_block < 0 || p.bkz_block == 1 || p.bkz_block > 40) return MSP_E_ARG;
     *k_out = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -789,8 +826,11 @@ int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_
     if (rc != MSP_OK) return rc;
     c->last_lll_iters = h[0].iters;
     const int s = lll_status(h[0].status);
-    if (s == MSP_OK) *k_out = h[0].kout;
-    return s;
+    if (s != MSP_OK) return s;
+    const int rb = bkz_after_lll(c, p, basis_dev, h[0].kout, n + 1, st);
+    if (rb != MSP_OK) return rb;
+    *k_out = h[0].kout;
+    return MSP_OK;
 }
 
 int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,
@@ -869,6 +909,7 @@ int msp_reduce_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const int
     msp_params_default(&p);
     if (pin) p = *pin;
     if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    if (p.bkz_block < 0 || p.bkz_block == 1 || p.bkz_block > 40) return MSP_E_ARG;
     *k_out = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -881,8 +922,11 @@ int msp_reduce_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const int
     if (rc != MSP_OK) return rc;
     c->last_lll_iters = h[0].iters;
     const int s = lll_status(h[0].status);
-    if (s == MSP_OK) *k_out = h[0].kout;
-    return s;
+    if (s != MSP_OK) return s;
+    const int rb = bkz_after_lll(c, p, basis_dev, h[0].kout, n + 1, st);
+    if (rb != MSP_OK) return rb;
+    *k_out = h[0].kout;
+    return MSP_OK;
 }
 
 int msp_enumerate_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int32_t *r_dev,

@@ -189,6 +189,20 @@ hipError_t sort_idx_asc(void *temp, size_t *temp_bytes, const int64_t *in, int64
 hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t *keys_out, int32_t *idx,
                         int32_t *perm, int64_t n, unsigned long long seed, int epoch, hipStream_t st);
 
+// BKZ of a kernel basis (bkz.hip), one wave, in place.
+struct BkzArgs {
+    int k, dim;
+    int64_t *B;                    // k x dim kernel basis (device), reduced in place
+    int beta, tours;               // block size, tour limit
+    double delta;                  // Lovasz parameter of the LLL inside
+    long long max_nodes;           // enumeration nodes per block SVP
+    long long max_lll_iters;       // LLL iterations over the whole run
+    int *out;                      // [0] status (0, -4 overflow, -10 iteration cap), [1] insertions
+    long long *nodes;              // [0] SVP nodes
+};
+hipError_t launch_bkz(const BkzArgs &a, hipStream_t st);
+size_t bkz_lds_bytes(int k);
+
 // Per-instance fields are read as base[i * stride] (in 4-byte units), so a
 // packed array of descriptor structs serves as the per-instance arrays.
 struct LllArgs {
