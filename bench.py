@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--orders", default="plain,learned", help="orders timed on the TTFS set")
     ap.add_argument("--batch", action="store_true",
                     help="also time the uneven 96-instance batch (msp_solve_batch) with autotuned root counts")
+    ap.add_argument("--bkz", type=int, default=0, help="BKZ block size for every reduction (0: LLL only)")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2508_08702_amd", "order_model.npy"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -148,7 +149,7 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
         d = torch.from_numpy(inst.d).to(dev)
         row = {"m": inst.m, "D": int(inst.D), "seed": int(inst.seed)}
         for name in names:
-            prm = M.msp_params_default(time_cap_ms=args.ttfs_cap_ms)
+            prm = M.msp_params_default(time_cap_ms=args.ttfs_cap_ms, bkz_block=args.bkz)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             Bk = M.msp_reduce(ctx, A, d, prm)
@@ -175,6 +176,7 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
         return statistics.median(v)
 
     out = {"set": f"{len(insts)} planted instances m={insts[0].m}, n={insts[0].n}, 4 each D=50/100/200",
+           "reduction": f"BKZ-{args.bkz}" if args.bkz else "LLL",
            "mode": "first", "cap_ms": args.ttfs_cap_ms,
            "median_end_to_end_ms": {n: med(n) for n in names},
            "censored": {n: sum(r[n]["censored"] for r in per) for n in names},
@@ -204,7 +206,7 @@ def main():
     dev = torch.device("cuda", 0)
     dev_in = [(torch.from_numpy(i.A).to(dev), torch.from_numpy(i.d).to(dev)) for i in insts]
     ctx = M.Context(0)
-    prm = M.msp_params_default(time_cap_ms=args.time_cap_ms)
+    prm = M.msp_params_default(time_cap_ms=args.time_cap_ms, bkz_block=args.bkz)
     out = torch.zeros((1 << 16, max(i.n for i in insts)), dtype=torch.uint8, device=dev)
 
     def step(record):
@@ -270,6 +272,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "mode": "all", "order": "plain",
+                   "reduction": f"BKZ-{args.bkz}" if args.bkz else "LLL",
                    "nodes_per_step": nodes // max(1, args.steps)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,

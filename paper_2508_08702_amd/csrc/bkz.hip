@@ -62,19 +62,27 @@ struct Bkz {
         __syncthreads();
     }
 
-    // Gram-Schmidt row i from the exact Gram row and rows < i (lane 0)
+    // Gram-Schmidt row i from the exact Gram row and rows < i:
+    // r_j = G_ij - sum_{l<j} mu_jl r_l, mu_ij = r_j / beta_j, beta_i = G_ii -
+    // sum_j mu_ij r_j.  The sums are split over the lanes (lane l keeps r_j
+    // for j = l mod 64 in r[]) and reduced across the wave.
     __device__ void gs_row(int i) {
-        if (lane == 0) {
-            double rr = 0.0;
-            for (int j = 0; j < i; ++j) {
-                double s = (double)gram(i, j);
-                for (int l = 0; l < j; ++l) s -= mu[trs(j, l)] * r[l];
+        double rr_part = 0.0;
+        for (int j = 0; j < i; ++j) {
+            double part = 0.0;
+            for (int l = lane; l < j; l += kW) part += mu[trs(j, l)] * r[l];
+            for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, kW);
+            const double s = (double)gram(i, j) - part;
+            const double m = s / bb[j];
+            if (lane == (j & (kW - 1))) {
                 r[j] = s;
-                mu[trs(i, j)] = s / bb[j];
-                rr += mu[trs(i, j)] * s;
+                mu[trs(i, j)] = m;
+                rr_part += m * s;
             }
-            bb[i] = (double)gram(i, i) - rr;
+            __syncthreads();
         }
+        for (int o = 32; o >= 1; o >>= 1) rr_part += __shfl_xor(rr_part, o, kW);
+        if (lane == 0) bb[i] = (double)gram(i, i) - rr_part;
         __syncthreads();
     }
 
@@ -152,6 +160,12 @@ __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
     double *cc = cl + k + 1;                               // per-level centres
     int *st = reinterpret_cast<int *>(cc + k);             // per-level zig-zag state: u1, step count
     if (z.lane == 0) z.flag[0] = 0;
+    // the basis itself in LDS when it fits (copied back at the end)
+    int64_t *Bs = reinterpret_cast<int64_t *>(st + 2 * k);  // 8-byte aligned: st follows doubles
+    if (a.b_in_lds) {
+        for (int e = z.lane; e < k * dim; e += kW) Bs[e] = a.B[e];
+        z.B = Bs;
+    }
     __syncthreads();
     long long budget = a.max_lll_iters;
     z.gram_all();
@@ -293,6 +307,10 @@ __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
         }
         if (!changed) break;
     }
+    if (a.b_in_lds) {
+        for (int e = z.lane; e < k * dim; e += kW) a.B[e] = Bs[e];
+        __syncthreads();
+    }
     if (z.lane == 0) {
         a.out[0] = z.flag[0] ? -4 : (budget > 0 ? 0 : -10);
         a.out[1] = (int)inserted;
@@ -302,12 +320,16 @@ __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
 
 size_t bkz_lds_bytes(int k) {
     return sizeof(long long) * (size_t)(k * (k + 1) / 2) + sizeof(double) * (size_t)(k * (k - 1) / 2 + 1 + 2 * k) +
-           sizeof(int) * (size_t)(2 * k + 2) + sizeof(double) * (size_t)(2 * k + 1) + sizeof(int) * (size_t)(2 * k) + 64;
+           sizeof(int) * (size_t)(2 * k + 2) + sizeof(double) * (size_t)(2 * k + 1) + sizeof(int) * (size_t)(2 * k + 2) +
+           64;
 }
 
-hipError_t launch_bkz(const BkzArgs &a, hipStream_t st) {
-    const size_t lds = bkz_lds_bytes(a.k);
+hipError_t launch_bkz(BkzArgs a, hipStream_t st) {
+    size_t lds = bkz_lds_bytes(a.k);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const size_t with_b = lds + sizeof(int64_t) * (size_t)a.k * a.dim;
+    a.b_in_lds = with_b <= 160 * 1024 ? 1 : 0;
+    if (a.b_in_lds) lds = with_b;
     hipError_t e = hipFuncSetAttribute((const void *)bkz_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bkz_kernel, dim3(1), dim3(kW), lds, st, a);

@@ -199,8 +199,9 @@ struct BkzArgs {
     long long max_lll_iters;       // LLL iterations over the whole run
     int *out;                      // [0] status (0, -4 overflow, -10 iteration cap), [1] insertions
     long long *nodes;              // [0] SVP nodes
+    int b_in_lds;                  // set by launch_bkz: the basis fits in LDS
 };
-hipError_t launch_bkz(const BkzArgs &a, hipStream_t st);
+hipError_t launch_bkz(BkzArgs a, hipStream_t st);
 size_t bkz_lds_bytes(int k);
 
 // Per-instance fields are read as base[i * stride] (in 4-byte units), so a
