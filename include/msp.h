@@ -104,7 +104,7 @@ typedef struct {
                            * (Section 3); -1 = no limit, at most 255            [-1] */
     int bkz_block;        /* msp_reduce: BKZ block size applied to the kernel
                            * basis after LLL (Section 2); 0 = LLL only, else 2..40 [0] */
-    int bkz_tours;        /* BKZ tour limit                                      [8] */
+    int bkz_tours;        /* BKZ tour limit                                      [4] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).

@@ -195,7 +195,7 @@ int msp_params_default(msp_params *p) {
     p->refine_keep = 0;
     p->disc_budget = -1;
     p->bkz_block = 0;
-    p->bkz_tours = 8;
+    p->bkz_tours = 4;
     return MSP_OK;
 }
 

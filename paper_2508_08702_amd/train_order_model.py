@@ -6,6 +6,7 @@ For every instance of the training set (planted market split instances,
 m in {6, 7, 8}, n = 10(m-1), D in {50, 100, 200}, seeds 4000-4191) this runs
 the exhaustive GPU enumeration with root tracing (msp_root_trace): each
 subtree root gets its 16 features and the label "a solution lies below".
+With --bkz the traced bases are BKZ-reduced first.
 The traces stay on the device; the model (16 -> 64 -> 64 -> 1, BF16 weights)
 is trained on them by the library's own kernels (msp_model_train) and its
 FP32 master weights are written with numpy.save.
@@ -32,9 +33,9 @@ from . import (Context, msp_model_get, msp_model_init, msp_model_train, msp_para
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_model.npy")
 
 
-def collect(ctx, insts, log=print):
+def collect(ctx, insts, log=print, bkz=0):
     dev = ctx.device
-    prm = msp_params_default(time_cap_ms=120000.0)
+    prm = msp_params_default(time_cap_ms=120000.0, bkz_block=bkz)
     feats, labels = [], []
     t0 = time.time()
     for i, inst in enumerate(insts):
@@ -56,9 +57,10 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--init-seed", type=int, default=1)
+    ap.add_argument("--bkz", type=int, default=0, help="BKZ block size of the traced bases (0: LLL)")
     args = ap.parse_args()
     ctx = Context(0)
-    F, Y = collect(ctx, mi.train_set(), log=lambda s: print(s, flush=True))
+    F, Y = collect(ctx, mi.train_set(), log=lambda s: print(s, flush=True), bkz=args.bkz)
     print(f"dataset: {F.shape[0]} roots, {int(Y.sum())} with a solution below", flush=True)
     msp_model_init(ctx, args.init_seed)
     t0 = time.time()
