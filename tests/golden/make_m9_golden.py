@@ -1,5 +1,5 @@
 """Write the exhaustive oracle result of one m=9 instance (a parity case at
-full size) to tests/golden/m9_seed4508.json.
+full size) to tests/golden/m9_seed<seed>.json.
 
     python tests/golden/make_m9_golden.py [--threads N] [--seed 4508 --D 200]
 

@@ -1,8 +1,9 @@
-"""Full-size parity: the exhaustive GPU walk of a planted m=9, n=80, D=200
-instance (seed 4508, the benchmark's instance) on the oracle's exact-LLL
-basis against the stored oracle result (tests/golden/m9_seed4508.json, written
-by tests/golden/make_m9_golden.py from oracle/ alone: about 1.9e11 nodes,
-an hour of CPU): the same solution set and the same search counters."""
+"""Full-size parity: the exhaustive GPU walk of planted m=9, n=80 instances
+(D=200 seed 4508, the benchmark's instance, and D=100 seed 4504) on the
+oracle's exact-LLL basis against the stored oracle results
+(tests/golden/m9_seed*.json, written by tests/golden/make_m9_golden.py from
+oracle/ alone: about 2e11 nodes, over an hour of CPU each): the same solution
+set and the same search counters."""
 from __future__ import annotations
 
 import json
@@ -18,14 +19,15 @@ from oracle import lattice as L
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m9_seed4508.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def test_m9_exhaustive_matches_stored_oracle_run():
+@pytest.mark.parametrize("name", ["m9_seed4508.json", "m9_seed4504.json"])
+def test_m9_exhaustive_matches_stored_oracle_run(name):
     import hashlib
 
     import paper_2508_08702_amd as M
-    g = json.load(open(GOLDEN))
+    g = json.load(open(os.path.join(GOLDEN_DIR, name)))
     inst = mi.msp_class(9, g["instance"]["D"], g["instance"]["seed"])
     P = L.prepare(inst.A, inst.d)
     digest = hashlib.sha256(np.ascontiguousarray(P.basis, dtype=np.int64).tobytes()).hexdigest()
@@ -36,7 +38,8 @@ def test_m9_exhaustive_matches_stored_oracle_run():
         A = torch.from_numpy(inst.A).to(dev)
         d = torch.from_numpy(inst.d).to(dev)
         Bk = torch.from_numpy(np.ascontiguousarray(P.basis)).to(dev)
-        print("  gpu exhaustive m=9 seed 4508 on the oracle basis", flush=True)
+        print(f"  gpu exhaustive m=9 D={g['instance']['D']} seed {g['instance']['seed']} on the oracle basis",
+              flush=True)
         r = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(time_cap_ms=110000.0))
         torch.cuda.synchronize()
         assert r.status == M.MSP_OK
