@@ -80,9 +80,9 @@ typedef struct {
     int *timed_out;
     const int64_t *cvec;    /* n, c_j = r_max / r_j for bounded variables;
                              * NULL: binary (r_max = c_j = 1)                 */
-    int disc_budget;        /* limited discrepancy search: at most this many
-                             * levels on a path take a value other than their
-                             * first zig-zag value; < 0: no limit             */
+    int disc_budget;        /* limited discrepancy search: the ranks of a
+                             * path's values in their levels' value orders
+                             * sum to at most this; < 0: no limit             */
 } orc_args;
 
 /* Subtree roots, stored flat: root r has prefix u[r*k + i] (i >= level),
@@ -217,10 +217,24 @@ static double centre(const orc_args *a, const int *u, int t) {
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-/* dsc: discrepancies on the path above level t (Section 3, limited
- * discrepancy search): a level whose value is not its first zig-zag value u1
- * counts one.  With a budget, a level stops at the first value that would
- * exceed it -- every later value of the level is a discrepancy as well. */
+/* Rank of u in its level's value order (Section 3, limited discrepancy
+ * search: a discrepancy is a departure from the value order, counted here as
+ * how far down the order the value lies).  On a top-zero level the order is
+ * 0, 1, 2, ... and the rank is u; otherwise the order is u1, u1+s, u1-s,
+ * u1+2s, ... and u1 + o has rank 2|o|-1 when o has the sign of s, else 2|o|.
+ * Values reached in one direction after a Hoelder failure keep their rank in
+ * that order, so ranks never decrease along a level. */
+static int zig_rank(int u, int u1, int s, int topzero) {
+    if (topzero) return u;
+    const int o = u - u1;
+    if (o == 0) return 0;
+    const int ao = o < 0 ? -o : o;
+    return ((o > 0) == (s > 0)) ? 2 * ao - 1 : 2 * ao;
+}
+
+/* dsc: discrepancies on the path above level t, the sum of the ranks of its
+ * values.  With a budget, a level stops at the first value whose rank would
+ * take the path beyond it; every later value of the level ranks higher. */
 static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, int topzero, int dsc) {
     const orc_args *a = W->a;
     const int dim = a->dim;
@@ -239,7 +253,8 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
     int u = u1;
     for (;;) {
         if (g_sh->stop) { W->u[t] = 0; return; }
-        if (a->disc_budget >= 0 && u != u1 && dsc >= a->disc_budget) break;
+        const int rank = zig_rank(u, u1, s, topzero);
+        if (a->disc_budget >= 0 && dsc + rank > a->disc_budget) break;
         const double x = (double)u + y;
         const double l = x * x * a->beta[t] + lpar;
         W->cnt[0]++;
@@ -270,9 +285,9 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
             W->cnt[2]++;
             if (W->lvl) W->lvl[t * 3 + 2]++;
             if (W->collect_level == t) {
-                push_root(W, w, l, topzero && u == 0, dsc + (u != u1));
+                push_root(W, w, l, topzero && u == 0, dsc + rank);
             } else {
-                enum_level(W, t - 1, w, l, topzero && u == 0, dsc + (u != u1));
+                enum_level(W, t - 1, w, l, topzero && u == 0, dsc + rank);
             }
         } else {
             W->cnt[3]++;

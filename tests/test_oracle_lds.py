@@ -1,7 +1,10 @@
-"""CPU pins of the oracle's limited discrepancy search (paper, Section 3): a
-path may take a value other than its level's first zig-zag value at most B
-times.  Pinned by an independent pure-Python recursion on small instances,
-by B >= depth reducing to the plain search, and by monotonicity in B."""
+"""CPU pins of the oracle's limited discrepancy search (paper, Section 3): the
+ranks of a path's values in their levels' value orders (u1, u1+s, u1-s, ...;
+0, 1, 2, ... on top-zero levels) sum to at most the budget B.  Pinned by an
+independent pure-Python recursion on small instances; by the solution set of
+each budget being exactly the solutions whose own path, recovered from the
+solution vector's basis coordinates, ranks within B; by a large budget
+reducing to the plain search; and by monotonicity in B."""
 from __future__ import annotations
 
 import numpy as np
@@ -11,6 +14,16 @@ import msp_instances as mi
 from oracle import enum as E
 from oracle import lattice as L
 from oracle import roots as RT
+
+
+def _rank(val, u1, s, topzero):
+    """Position of val in its level's value order."""
+    if topzero:
+        return val
+    o = val - u1
+    if o == 0:
+        return 0
+    return 2 * abs(o) - 1 if (o > 0) == (s > 0) else 2 * abs(o)
 
 
 def _python_lds(P, B, eps=E.EPS):
@@ -33,7 +46,8 @@ def _python_lds(P, B, eps=E.EPS):
             onedir, dr = False, 0
         off, val = 0, u1
         while True:
-            if B >= 0 and val != u1 and dsc >= B:
+            rank = _rank(val, u1, s, topzero)
+            if B >= 0 and dsc + rank > B:
                 break
             x = float(val) + y
             l = x * x * float(P.beta[t]) + lpar
@@ -53,7 +67,7 @@ def _python_lds(P, B, eps=E.EPS):
                     dr = 1 if float(val) - c > 0.0 else -1
                     continue
                 cnt[2] += 1
-                level(t - 1, w, l, topzero and val == 0, dsc + (val != u1))
+                level(t - 1, w, l, topzero and val == 0, dsc + rank)
             else:
                 cnt[3] += 1
                 v = np.array(u, dtype=np.int64) @ P.basis
@@ -98,6 +112,41 @@ def test_budget_is_monotone_and_reaches_the_plain_search(m, D, seed):
         assert r.nodes >= prev_nodes and prev_set <= s
         assert s <= {tuple(x) for x in full.solutions}
         prev_nodes, prev_set = r.nodes, s
-    r = E.enumerate_prepared(P, split=4, disc_budget=P.k)
+    r = E.enumerate_prepared(P, split=4, disc_budget=1 << 20)
     assert (r.evals, r.nodes, r.expansions, r.leaves) == (full.evals, full.nodes, full.expansions, full.leaves)
     assert np.array_equal(r.solutions, full.solutions)
+
+
+def _path_ranks(P, x):
+    """Ranks of the values on the path that leads to solution x, top level
+    first: u solves u B = v with v = (2x - 1, 1) (the enumerated sign has a
+    positive top nonzero u); the centres along the path follow from u alone."""
+    v = np.concatenate([2 * x.astype(np.int64) - 1, [1]])
+    B = np.asarray(P.basis, dtype=np.int64)
+    u = np.rint(np.linalg.lstsq(B.T.astype(np.float64), v.astype(np.float64), rcond=None)[0]).astype(np.int64)
+    assert np.array_equal(u @ B, v)
+    if u[np.nonzero(u)[0][-1]] < 0:
+        u = -u
+    out, topzero = [], True
+    for t in range(P.k - 1, -1, -1):
+        c = -RT.centre(P, [int(e) for e in u], t)
+        u1 = int(np.rint(c))
+        out.append(_rank(int(u[t]), u1, 1 if float(u1) - c <= 0.0 else -1, topzero))
+        topzero = topzero and u[t] == 0
+    return out
+
+
+# instances with a solution whose path takes a value of rank 2 or more, where
+# counting ranks and counting departures from u1 give different budgets
+@pytest.mark.parametrize("m,D,seed", [(5, 50, 1), (5, 50, 2), (5, 50, 14)])
+def test_each_budget_finds_exactly_the_solutions_ranked_within_it(m, D, seed):
+    inst = mi.msp_class(m, D, seed)
+    P = L.prepare(inst.A, inst.d)
+    full = E.enumerate_prepared(P, split=4, threads=4)
+    paths = {tuple(x): _path_ranks(P, x) for x in full.solutions}
+    assert any(max(r) >= 2 for r in paths.values())
+    ranks = {x: sum(r) for x, r in paths.items()}
+    assert len(set(ranks.values())) >= 2                 # the budgets separate the solutions
+    for B in range(0, max(ranks.values()) + 2):
+        r = E.enumerate_prepared(P, split=4, threads=4, disc_budget=B)
+        assert {tuple(x) for x in r.solutions} == {x for x, c in ranks.items() if c <= B}, B
