@@ -57,11 +57,17 @@ enum {
 
 #define MSP_MAX_N 127        /* largest n accepted (n + 1 <= 128)                */
 
-/* enumeration modes: every solution; a first solution by one walk; a first
- * solution by limited discrepancy search (Section 3): walks that admit at
- * most B = 0, 1, 2, ... levels whose value is not their first zig-zag value,
- * then one walk without a budget (exhaustive), stopping at the first pass with
- * a hit.  msp_stats then sums the passes (stages = passes run). */
+/* Discrepancies (limited discrepancy search, Section 3).  Each level tries its
+ * values in a fixed order: u1, u1+s, u1-s, u1+2s, ... around the centre, or
+ * 0, 1, 2, ... while every higher value is zero.  Taking the value of rank r in
+ * that order costs r discrepancies, and a path's discrepancies are the sum
+ * over its levels.
+ *
+ * enumeration modes: every solution; a first solution by one walk; a first
+ * solution by limited discrepancy search: walks that admit paths of at most
+ * B = 0, 1, 2, ..., min(k, 255) discrepancies, then one walk without a budget
+ * (exhaustive), stopping at the first pass with a hit.  msp_stats then sums
+ * the passes (stages = passes run). */
 enum { MSP_ALL = 0, MSP_FIRST = 1, MSP_LDS = 2 };
 /* Orders in which the subtree roots are walked.  The order changes only
  * which solutions MSP_FIRST meets first and how soon; MSP_ALL returns the same
@@ -69,8 +75,7 @@ enum { MSP_ALL = 0, MSP_FIRST = 1, MSP_LDS = 2 };
  *   MSP_PLAIN        depth-first order (the order of Algorithm 1)
  *   MSP_LEARNED      best score first under the context's root-scoring model
  *                    (msp_model_init / msp_model_set / msp_model_train)
- *   MSP_DISCREPANCY  fewest discrepancies first -- roots whose prefix departs
- *                    least often from each level's first zig-zag value -- then
+ *   MSP_DISCREPANCY  fewest discrepancies on the root's prefix first, then
  *                    depth-first: limited discrepancy search (Section 3)
  *                    applied to the roots */
 enum { MSP_PLAIN = 0, MSP_LEARNED = 1, MSP_DISCREPANCY = 2 };
@@ -101,7 +106,7 @@ typedef struct {
     int refine_keep;      /* best nodes expanded further per stage; 0 = auto
                            * (256 per CU)                                        [0] */
     int disc_budget;      /* at most this many discrepancies on any walked path
-                           * (Section 3); -1 = no limit, at most 255            [-1] */
+                           * (see above; Section 3); -1 = no limit, at most 255 [-1] */
     int bkz_block;        /* msp_reduce: BKZ block size applied to the kernel
                            * basis after LLL (Section 2); 0 = LLL only, else 2..40 [0] */
     int bkz_tours;        /* BKZ tour limit                                      [4] */

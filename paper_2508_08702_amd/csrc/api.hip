@@ -640,8 +640,8 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
 
 // Limited discrepancy search for a first solution (paper, Section 3): walks
 // with discrepancy budget B = 0, 1, 2, ... (each a first-solution walk that
-// admits at most B levels off their first zig-zag value), then one walk
-// without a budget, which is exhaustive.  Stops at the first pass with a
+// admits paths whose values' ranks in their levels' value orders sum to at
+// most B), then one walk without a budget, which is exhaustive.  Stops at the first pass with a
 // hit; counters and times are summed over the passes (stages = passes run).
 static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int64_t *basis_dev,
                       int k, int order, const msp_params *pin, uint8_t *x_dev, int64_t cap, int64_t *n_found,

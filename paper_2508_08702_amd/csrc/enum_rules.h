@@ -84,6 +84,18 @@ __device__ __forceinline__ int zig_next(const Zig &z, int u) {
     return z.u1 + no;
 }
 
+// Rank of u in the level's value order (limited discrepancy search, Section 3:
+// the discrepancy cost of taking u): u on a top-zero level, else 0 for u1 and
+// 2|o|-1 or 2|o| for u1 + o on the side of s or the other side.  Ranks never
+// decrease along a level, one-direction runs included.
+__device__ __forceinline__ int zig_rank(const Zig &z, int u, bool topzero) {
+    if (topzero) return u;
+    const int o = u - z.u1;
+    if (o == 0) return 0;
+    const int ao = o < 0 ? -o : o;
+    return ((o > 0) == (z.s > 0)) ? 2 * ao - 1 : 2 * ao;
+}
+
 // Direction kept after the first Hoelder failure: the side of c that u is on.
 __device__ __forceinline__ int side_of(int u, double y) { return add_rn((double)u, y) > 0.0 ? 1 : -1; }
 

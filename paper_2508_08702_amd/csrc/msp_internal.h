@@ -16,9 +16,9 @@ namespace msp {
 //                         w[r .. r+DIMP) without wrapping)
 //   l   f64   [cap]       ||w||^2 by the partial-norm recurrence
 //   tz  uint8 [cap]       1 while every u above the record's level is zero
-//   dsc uint8 [cap]       discrepancies on the prefix (levels whose value is
-//                         not their first zig-zag value; limited discrepancy
-//                         search, paper Section 3)
+//   dsc uint8 [cap]       discrepancies on the prefix: the sum of the ranks of
+//                         its values in their levels' value orders (limited
+//                         discrepancy search, paper Section 3), capped at 255
 struct Frontier {
     int8_t *u;
     double *w;

@@ -146,13 +146,14 @@ hipError_t launch_root_labels(Frontier roots, int64_t np, int k, int L, const in
     return hipGetLastError();
 }
 
-// Discrepancy order key: minus the number of discrepancies (exact small
-// integers in FP32), so a descending stable sort takes the fewest first and
-// keeps depth-first order among equals.
+// Discrepancy order key: minus the prefix's discrepancies, the rank sum
+// recovered from the mean rank (an exact small integer in FP32), so a
+// descending stable sort takes the fewest first and keeps depth-first order
+// among equals.
 __global__ void disc_key_kernel(const float *feat, int64_t np, int levels, float *key) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= np) return;
-    key[r] = -rintf(feat[r * kNumFeat + 4] * (float)levels);
+    key[r] = -rintf(feat[r * kNumFeat + 3] * (float)levels);
 }
 
 hipError_t launch_disc_keys(const float *feat, int64_t np, int levels, float *key, hipStream_t st) {

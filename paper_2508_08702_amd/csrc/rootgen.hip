@@ -36,8 +36,10 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         int64_t slot = WRITE ? a.offs[p] : 0;
         int64_t nch = 0;
         for (;;) {
-            // a budget stops the level at the first value that would exceed it
-            if (a.budget >= 0 && u != z.u1 && pd >= a.budget) break;
+            // a budget stops the level at the first value whose rank would
+            // take the path beyond it
+            const int rank = zig_rank(z, u, tz);
+            if (a.budget >= 0 && pd + rank > a.budget) break;
             const double x = add_rn((double)u, y);
             const double l = partial_norm(x, beta, lpar);
             ++ce;
@@ -68,7 +70,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
                     for (int j = a.dimp; j < ws; ++j) wc[j] = wc[j - a.dimp];
                     a.ch.l[slot] = l;
                     a.ch.tz[slot] = (tz && u == 0) ? 1 : 0;
-                    a.ch.dsc[slot] = (uint8_t)(pd + (u != z.u1 ? 1 : 0));
+                    a.ch.dsc[slot] = (uint8_t)(pd + rank < 255 ? pd + rank : 255);
                     ++slot;
                 }
                 ++nch;

@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     double y = 0.0, lpar = 0.0, lcur = 0.0, bt = 1.0;
     double Py = 0.0, Pl = 0.0, Pbt = 1.0;  // cached state of level t+1
     int Pu = 0, Pf = 0, Pdirty = 0;  // Pdirty: cache differs from stack entry t+1
-    // discrepancies on the path above level t, and above level t+1 (Pdsc)
+    // discrepancies (rank sums) on the path above level t, and above level t+1 (Pdsc)
     int dsc = 0, Pdsc = 0;
     const int budget = a.budget;
     unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     const int odD = fD & F_ONEDIR, drD = (fD & F_DIRPOS) ? 1 : -1;
                     const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
                     un = odD ? uD + drD : zig_next(zD, uD);
-                    if (budget >= 0 && un != zD.u1 && dD >= budget) {
+                    if (budget >= 0 && dD + zig_rank(zD, un, (fD & F_TZ) != 0) > budget) {
                         // the budget ends level D before its next value
                         top = D - 1;
                         cand = false;
@@ -446,8 +446,9 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             double coef = 0.0;
             bool popped = false;
             while (state == RUN) {
-                // a discrepancy budget ends the level at the first value beyond it
-                if (!fex && budget >= 0 && u != z.u1 && dsc >= budget) fex = 1;
+                // a discrepancy budget ends the level at the first value whose
+                // rank takes the path beyond it
+                if (!fex && budget >= 0 && dsc + zig_rank(z, u, tz != 0) > budget) fex = 1;
                 if (!fex) {
                     const double x = add_rn((double)u, y);
                     const double l = partial_norm(x, bt, lpar);
@@ -559,7 +560,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         }
                         Pdirty = 1;
                         Pdsc = dsc;
-                        dsc += (u != z.u1) ? 1 : 0;
+                        dsc += zig_rank(z, u, tz != 0);
                         Py = y;
                         Pl = lpar;
                         Pbt = bt;
