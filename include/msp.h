@@ -97,7 +97,8 @@ typedef struct {
     int split_depth;      /* levels enumerated before the subtree split; -1 = auto [-1] */
     int block;            /* walk kernel workgroup size cap (256|512); 0 = auto [0] */
     int target_roots;     /* root count the automatic split aims for; 0 = auto:
-                           * 512 per CU for MSP_ALL, 16384 per CU for MSP_FIRST [0] */
+                           * 512 per CU for MSP_ALL, 16384 per CU for MSP_FIRST,
+                           * 2048 per CU for each MSP_LDS pass                 [0] */
     int hoelder;          /* 1: apply the Hoelder test (Thm 2)                  [1] */
     int onedir;           /* 1: apply the one-direction cut (Section 2)         [1] */
     double time_cap_ms;   /* enumeration wall-time cap; <= 0 = none             [0] */
@@ -110,6 +111,9 @@ typedef struct {
     int bkz_block;        /* msp_reduce: BKZ block size applied to the kernel
                            * basis after LLL (Section 2); 0 = LLL only, else 2..40 [0] */
     int bkz_tours;        /* BKZ tour limit                                      [4] */
+    int restarts;         /* msp_solve_first: shuffled copies of the instance,
+                           * 1..64 (copy 0 keeps the given variable order)       [1] */
+    uint32_t restart_seed;/* msp_solve_first: seed of the shuffles               [1] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).
@@ -135,6 +139,8 @@ typedef struct {
     int32_t stages;          /* refinement stages run (0 without refinement)     */
     int32_t root_level;      /* level of the walked roots (deepest stage)        */
     int64_t initial_items;   /* work items before the walk: roots + leftovers    */
+    int32_t copy;            /* msp_solve_first: the copy that hit (-1: none)    */
+    int32_t copies;          /* msp_solve_first: copies reduced and searched     */
 } msp_stats;
 
 /* Fill `p` with the defaults.  Returns MSP_OK or MSP_E_ARG (p == NULL). */
@@ -228,6 +234,27 @@ typedef struct {
 int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const int32_t *A_dev,
                     const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
                     int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
+
+/* A first solution from A and d alone, by limited discrepancy search over
+ * randomly shuffled copies of the instance (Section 4 proposes running the
+ * method on randomly reordered input bases at once; here the copies share one
+ * GPU).  Copy 0 is the instance as given; copy i > 0 permutes the variables by
+ * a shuffle drawn from p->restart_seed and i.  All p->restarts copies are
+ * reduced together (one LLL launch, then one BKZ launch when p->bkz_block >= 2,
+ * one wave per copy).  The LDS passes then run by rising budget B, copy after
+ * copy within each B (each pass as by msp_enumerate with MSP_LDS, in `order`),
+ * and stop at the first verified hit.  The final unlimited pass runs on copy 0
+ * only and is exhaustive.  x_dev receives up to `cap` rows in the caller's
+ * variable order, *n_found their count (0 only if the instance has no
+ * solution, or on MSP_E_TIMEOUT), stats the summed counters with copy and
+ * copies set.  A copy whose reduction fails (e.g. MSP_E_NOT_ISOLATED) is
+ * skipped; the call fails with that status only if copy 0 fails.
+ * p->time_cap_ms bounds the search after the reduction.
+ * Errors: those of msp_reduce and msp_enumerate; MSP_E_ARG for restarts
+ * outside 1..64. */
+int msp_solve_first(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev, int order,
+                    const msp_params *p, uint8_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats,
+                    void *stream);
 
 /* Autotuner (a project addition).  Reduces the `batch` tuning instances once
  * (as msp_solve_batch does), then for each candidate root count -- 128, 256,

@@ -42,7 +42,7 @@ MSP_MODEL_NPARAM = 5313
 # every symbol include/msp.h declares
 EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
-    "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_strerror",
+    "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_solve_first", "msp_strerror",
     "msp_reduce_bounded", "msp_enumerate_bounded", "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
     "msp_model_grad", "msp_train_params_default", "msp_model_train",
 )
@@ -60,7 +60,7 @@ class Params(C.Structure):
         ("split_depth", C.c_int), ("block", C.c_int), ("target_roots", C.c_int),
         ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
         ("refine", C.c_int), ("refine_keep", C.c_int), ("disc_budget", C.c_int),
-        ("bkz_block", C.c_int), ("bkz_tours", C.c_int),
+        ("bkz_block", C.c_int), ("bkz_tours", C.c_int), ("restarts", C.c_int), ("restart_seed", C.c_uint32),
     ]
 
 
@@ -72,7 +72,7 @@ class Stats(C.Structure):
         ("reduce_ms", C.c_double), ("gs_ms", C.c_double), ("rootgen_ms", C.c_double),
         ("ordering_ms", C.c_double), ("kernel_ms", C.c_double), ("ttfs_ms", C.c_double),
         ("total_ms", C.c_double), ("stages", C.c_int32), ("root_level", C.c_int32),
-        ("initial_items", C.c_int64),
+        ("initial_items", C.c_int64), ("copy", C.c_int32), ("copies", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -111,6 +111,9 @@ def _load() -> C.CDLL:
     lib.msp_enumerate.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, i64,
                                   C.POINTER(i64), C.POINTER(Stats), vp]
     lib.msp_enumerate.restype = i32
+    lib.msp_solve_first.argtypes = [vp, i32, i32, vp, vp, i32, C.POINTER(Params), vp, i64, C.POINTER(i64),
+                                    C.POINTER(Stats), vp]
+    lib.msp_solve_first.restype = i32
     lib.msp_solve_batch.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params), vp,
                                     C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(Stats), vp]
     lib.msp_solve_batch.restype = i32
@@ -293,6 +296,33 @@ def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.T
                             out.data_ptr(), int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
     if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
         raise MspError(rc, "msp_enumerate")
+    rows = min(nf.value, cap)
+    return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())
+
+
+def msp_solve_first(ctx: Context, A: torch.Tensor, d: torch.Tensor, *, order: int = MSP_PLAIN,
+                    params: Params | None = None, cap: int = 64, out: torch.Tensor | None = None,
+                    raise_on_error: bool = True) -> EnumResult:
+    """A first solution of A x = d by limited discrepancy search over
+    params.restarts shuffled copies reduced together (rows in the given
+    variable order).  MSP_CAPACITY and MSP_TIMEOUT are reported in ``status``;
+    other errors raise unless ``raise_on_error`` is False."""
+    m, n = A.shape
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    if out is None:
+        out = torch.zeros((max(cap, 1), n), dtype=torch.uint8, device=dev)
+    else:
+        _dev_ptr(out, torch.uint8, dev, "out")
+        cap = min(cap, out.shape[0])
+    p = params if params is not None else msp_params_default()
+    nf = C.c_int64(0)
+    st = Stats()
+    rc = lib().msp_solve_first(ctx.handle, m, n, ap, dp, int(order), C.byref(p), out.data_ptr(), int(cap),
+                               C.byref(nf), C.byref(st), _stream_handle(dev))
+    if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
+        raise MspError(rc, "msp_solve_first")
     rows = min(nf.value, cap)
     return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())
 

@@ -133,6 +133,7 @@ struct msp_ctx {
     Buf left_u, left_meta, top_idx;  // refinement: stage leftovers, best-node indices
     Buf cvec, rmax;                  // bounded variables: c_j and r_max of the last bounds
     Buf bkz_out, bkz_save;           // BKZ status words and the LLL basis kept for a fallback
+    Buf rs_A, rs_perm, rs_basis, rs_x;  // msp_solve_first: shuffled copies, their bases, a hit's rows
     // roots of the last enumeration (for tracing)
     int last_cur = 0, last_L = 0, last_k = 0, last_dim = 0, last_ws = 0, last_m = 0;
     int64_t last_np = 0;
@@ -196,6 +197,8 @@ int msp_params_default(msp_params *p) {
     p->disc_budget = -1;
     p->bkz_block = 0;
     p->bkz_tours = 4;
+    p->restarts = 1;
+    p->restart_seed = 1;
     return MSP_OK;
 }
 
@@ -264,6 +267,10 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->rmax.release();
     c->bkz_out.release();
     c->bkz_save.release();
+    c->rs_A.release();
+    c->rs_perm.release();
+    c->rs_basis.release();
+    c->rs_x.release();
     c->counts.release();
     c->offs.release();
     c->stack.release();
@@ -659,6 +666,10 @@ static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int6
     for (int B = 0; B <= maxb + 1; ++B) {
         msp_params q = p;
         q.disc_budget = B <= maxb ? B : -1;
+        // A budgeted tree is narrow, so reaching the first-solution root count
+        // takes a deep split, and root generation is paid again on every pass.
+        // Eight roots per walker keep that small; donation balances the walk.
+        if (q.target_roots == 0) q.target_roots = 8 * 256 * c->num_cus;
         if (p.time_cap_ms > 0) {
             const double used =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -777,34 +788,42 @@ int run_lll(msp_ctx *c, std::vector<LllDesc> &h, const int32_t *A_dev, const int
 }
 }  // namespace
 
-// BKZ of an extracted kernel basis in place (k x dim); keeps the LLL basis
-// when an entry would outgrow the exact Gram.
-static int bkz_after_lll(msp_ctx *c, const msp_params &p, int64_t *basis_dev, int k, int dim, hipStream_t st) {
-    if (p.bkz_block < 2 || k < 2) return MSP_OK;
+// BKZ of `count` extracted kernel bases in place (each k x dim, basis i at
+// basis_dev + i * bstride), one workgroup per basis in one launch; a basis
+// whose entries would outgrow the exact Gram keeps its LLL form.
+static int bkz_after_lll(msp_ctx *c, const msp_params &p, int64_t *basis_dev, int k, int dim, hipStream_t st,
+                         int count = 1, int64_t bstride = 0) {
+    if (p.bkz_block < 2 || k < 2 || count < 1) return MSP_OK;
     if (bkz_lds_bytes(k) > 160 * 1024) return MSP_E_UNSUPPORTED;
+    if (count == 1) bstride = (int64_t)k * dim;
     const size_t nb = (size_t)k * dim * sizeof(int64_t);
-    MSP_TRY(c->bkz_save.ensure(nb));
-    MSP_TRY(c->bkz_out.ensure(64));
-    MSP_TRY(hipMemcpyAsync(c->bkz_save.p, basis_dev, nb, hipMemcpyDeviceToDevice, st));
+    const size_t all = ((size_t)(count - 1) * bstride + (size_t)k * dim) * sizeof(int64_t);
+    MSP_TRY(c->bkz_save.ensure(all));
+    MSP_TRY(c->bkz_out.ensure((size_t)count * (2 * sizeof(int) + sizeof(long long))));
+    MSP_TRY(hipMemcpyAsync(c->bkz_save.p, basis_dev, all, hipMemcpyDeviceToDevice, st));
     BkzArgs b{};
     b.k = k;
     b.dim = dim;
     b.B = basis_dev;
+    b.bstride = bstride;
+    b.count = count;
     b.beta = p.bkz_block;
     b.tours = p.bkz_tours > 0 ? p.bkz_tours : 1;
     b.delta = p.delta;
     b.max_nodes = 1ll << 18;
     b.max_lll_iters = 1ll << 16;
-    b.out = c->bkz_out.as<int>();
-    b.nodes = reinterpret_cast<long long *>(c->bkz_out.as<int>() + 4);
+    b.nodes = c->bkz_out.as<long long>();
+    b.out = reinterpret_cast<int *>(b.nodes + count);
     MSP_TRY(launch_bkz(b, st));
-    int out[2] = {0, 0};
-    MSP_TRY(hipMemcpyAsync(out, b.out, sizeof(out), hipMemcpyDeviceToHost, st));
+    std::vector<int> out((size_t)2 * count);
+    MSP_TRY(hipMemcpyAsync(out.data(), b.out, sizeof(int) * out.size(), hipMemcpyDeviceToHost, st));
     MSP_TRY(hipStreamSynchronize(st));
-    if (out[0] == -4) {  // entries too large for the exact Gram: keep the LLL basis
-        MSP_TRY(hipMemcpyAsync(basis_dev, c->bkz_save.p, nb, hipMemcpyDeviceToDevice, st));
-        MSP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) {
+        if (out[2 * i] != -4) continue;  // entries too large for the exact Gram: keep the LLL basis
+        MSP_TRY(hipMemcpyAsync(basis_dev + (size_t)i * bstride, c->bkz_save.as<int64_t>() + (size_t)i * bstride, nb,
+                               hipMemcpyDeviceToDevice, st));
     }
+    MSP_TRY(hipStreamSynchronize(st));
     return MSP_OK;
 }
 
@@ -831,6 +850,146 @@ int msp_reduce(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_
     if (rb != MSP_OK) return rb;
     *k_out = h[0].kout;
     return MSP_OK;
+}
+
+// Shuffle of the n variables for copy r of msp_solve_first: identity for r = 0,
+// else Fisher-Yates driven by splitmix64 of (seed, r).
+static void restart_perm(uint32_t seed, int r, int n, int32_t *perm) {
+    for (int j = 0; j < n; ++j) perm[j] = j;
+    if (r == 0) return;
+    uint64_t x = ((uint64_t)seed << 32) ^ (uint64_t)(uint32_t)r;
+    auto next = [&x]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (int j = n - 1; j > 0; --j) {
+        const int i = (int)(next() % (uint64_t)(j + 1));
+        std::swap(perm[i], perm[j]);
+    }
+}
+
+int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, int order,
+                    const msp_params *pin, uint8_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats,
+                    void *stream) {
+    if (!c || !A_dev || !d_dev || !n_found || cap < 0 || (cap > 0 && !x_dev)) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
+    msp_params p;
+    msp_params_default(&p);
+    if (pin) p = *pin;
+    if (p.restarts < 1 || p.restarts > 64) return MSP_E_ARG;
+    if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    if (p.bkz_block < 0 || p.bkz_block == 1 || p.bkz_block > 40) return MSP_E_ARG;
+    *n_found = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point a) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+    };
+    const int R = p.restarts;
+    const size_t mn = (size_t)m * n, bsz = (size_t)(n + 1) * (n + 1);
+    // ---- the copies and their reduction, all at once ----
+    std::vector<int32_t> perm((size_t)R * n);
+    for (int r = 0; r < R; ++r) restart_perm(p.restart_seed, r, n, perm.data() + (size_t)r * n);
+    MSP_TRY(c->rs_perm.ensure(perm.size() * sizeof(int32_t)));
+    MSP_TRY(c->rs_A.ensure((size_t)R * mn * sizeof(int32_t)));
+    MSP_TRY(c->rs_basis.ensure((size_t)R * bsz * sizeof(int64_t)));
+    MSP_TRY(c->rs_x.ensure((size_t)std::max<int64_t>(cap, 1) * n));
+    const int32_t *perm_dev = c->rs_perm.as<int32_t>();
+    int32_t *A_cp = c->rs_A.as<int32_t>();
+    int64_t *bases = c->rs_basis.as<int64_t>();
+    MSP_TRY(hipMemcpyAsync(c->rs_perm.p, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    MSP_TRY(launch_permute_cols(A_dev, m, n, perm_dev, R, A_cp, st));
+    std::vector<LllDesc> h(R);
+    for (int r = 0; r < R; ++r) h[r] = LllDesc{m, n, (int64_t)(r * mn), 0, 0, (int64_t)(r * bsz), 0, 0, 0};
+    int rc = run_lll(c, h, A_cp, d_dev, bases, p, st);
+    if (rc != MSP_OK) return rc;
+    const int s0 = lll_status(h[0].status);
+    if (s0 != MSP_OK) return s0;
+    const int k = h[0].kout;
+    std::vector<char> ok(R);
+    int nok = 0;
+    for (int r = 0; r < R; ++r) nok += (ok[r] = lll_status(h[r].status) == MSP_OK && h[r].kout == k);
+    if (nok == R) {
+        rc = bkz_after_lll(c, p, bases, k, n + 1, st, R, (int64_t)bsz);
+    } else {
+        for (int r = 0; r < R && rc == MSP_OK; ++r)
+            if (ok[r]) rc = bkz_after_lll(c, p, bases + (size_t)r * bsz, k, n + 1, st);
+    }
+    if (rc != MSP_OK) return rc;
+    msp_stats acc;
+    std::memset(&acc, 0, sizeof(acc));
+    acc.reduce_ms = ms_since(t0);
+    acc.ttfs_ms = -1.0;
+    acc.copy = -1;
+    acc.copies = nok;
+    // ---- LDS passes by rising budget, copy after copy within each budget ----
+    const auto ts = std::chrono::steady_clock::now();
+    const int maxb = std::min(k, 255);
+    int passes = 0;
+    bool done = false;
+    for (int B = 0; B <= maxb + 1 && !done; ++B) {
+        for (int r = 0; r < R && !done; ++r) {
+            if (!ok[r]) continue;
+            if (B > maxb && r > 0) break;  // the unlimited pass: copy 0 only, exhaustive
+            msp_params q = p;
+            q.disc_budget = B <= maxb ? B : -1;
+            if (q.target_roots == 0) q.target_roots = 8 * 256 * c->num_cus;
+            if (p.time_cap_ms > 0) {
+                const double used = ms_since(ts);
+                if (used >= p.time_cap_ms) {
+                    rc = MSP_E_TIMEOUT;
+                    done = true;
+                    break;
+                }
+                q.time_cap_ms = p.time_cap_ms - used;
+            }
+            const double before = ms_since(t0);
+            int64_t nf = 0;
+            msp_stats sti;
+            std::memset(&sti, 0, sizeof(sti));
+            rc = enumerate_impl(c, m, n, A_cp + (size_t)r * mn, d_dev, bases + (size_t)r * bsz, k, MSP_FIRST, order,
+                                &q, r == 0 ? x_dev : c->rs_x.as<uint8_t>(), cap, &nf, &sti, stream);
+            ++passes;
+            acc.evals += sti.evals;
+            acc.nodes += sti.nodes;
+            acc.expansions += sti.expansions;
+            acc.leaves += sti.leaves;
+            acc.items += sti.items;
+            acc.roots = sti.roots;
+            acc.split_depth = sti.split_depth;
+            acc.k = sti.k;
+            acc.block = sti.block;
+            acc.root_level = sti.root_level;
+            acc.initial_items = sti.initial_items;
+            acc.gs_ms += sti.gs_ms;
+            acc.rootgen_ms += sti.rootgen_ms;
+            acc.ordering_ms += sti.ordering_ms;
+            acc.kernel_ms += sti.kernel_ms;
+            if (rc != MSP_OK) {
+                done = true;
+                break;
+            }
+            if (nf > 0) {
+                if (r > 0 && cap > 0) {
+                    MSP_TRY(launch_unpermute_rows(c->rs_x.as<uint8_t>(), std::min(nf, cap), n,
+                                                  perm_dev + (size_t)r * n, x_dev, st));
+                    MSP_TRY(hipStreamSynchronize(st));
+                }
+                *n_found = nf;
+                acc.copy = r;
+                acc.ttfs_ms =
+                    before + (sti.ttfs_ms >= 0.0 ? sti.ttfs_ms + sti.gs_ms + sti.rootgen_ms : sti.total_ms);
+                done = true;
+            }
+        }
+    }
+    acc.stages = passes;
+    acc.total_ms = ms_since(t0);
+    if (stats) *stats = acc;
+    return rc;
 }
 
 int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,

@@ -143,11 +143,12 @@ struct Bkz {
 
 __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int k = a.k, dim = a.dim;
+    const int k = a.k, dim = a.dim, inst = blockIdx.x;
+    int64_t *Bg = a.B + (size_t)inst * a.bstride;
     Bkz z;
     z.k = k;
     z.dim = dim;
-    z.B = a.B;
+    z.B = Bg;
     z.lane = threadIdx.x;
     z.G = reinterpret_cast<long long *>(smem);
     z.mu = reinterpret_cast<double *>(z.G + k * (k + 1) / 2);
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
     // the basis itself in LDS when it fits (copied back at the end)
     int64_t *Bs = reinterpret_cast<int64_t *>(st + 2 * k);  // 8-byte aligned: st follows doubles
     if (a.b_in_lds) {
-        for (int e = z.lane; e < k * dim; e += kW) Bs[e] = a.B[e];
+        for (int e = z.lane; e < k * dim; e += kW) Bs[e] = Bg[e];
         z.B = Bs;
     }
     __syncthreads();
@@ -308,13 +309,13 @@ __global__ void __launch_bounds__(kW) bkz_kernel(BkzArgs a) {
         if (!changed) break;
     }
     if (a.b_in_lds) {
-        for (int e = z.lane; e < k * dim; e += kW) a.B[e] = Bs[e];
+        for (int e = z.lane; e < k * dim; e += kW) Bg[e] = Bs[e];
         __syncthreads();
     }
     if (z.lane == 0) {
-        a.out[0] = z.flag[0] ? -4 : (budget > 0 ? 0 : -10);
-        a.out[1] = (int)inserted;
-        a.nodes[0] = nodes_total;
+        a.out[2 * inst] = z.flag[0] ? -4 : (budget > 0 ? 0 : -10);
+        a.out[2 * inst + 1] = (int)inserted;
+        a.nodes[inst] = nodes_total;
     }
 }
 
@@ -332,7 +333,8 @@ hipError_t launch_bkz(BkzArgs a, hipStream_t st) {
     if (a.b_in_lds) lds = with_b;
     hipError_t e = hipFuncSetAttribute((const void *)bkz_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bkz_kernel, dim3(1), dim3(kW), lds, st, a);
+    if (a.count < 1 || (a.count > 1 && a.bstride < (int64_t)a.k * a.dim)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bkz_kernel, dim3(a.count), dim3(kW), lds, st, a);
     return hipGetLastError();
 }
 

@@ -192,16 +192,26 @@ hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t
 // BKZ of a kernel basis (bkz.hip), one wave, in place.
 struct BkzArgs {
     int k, dim;
-    int64_t *B;                    // k x dim kernel basis (device), reduced in place
+    int64_t *B;                    // count k x dim kernel bases (device), reduced in place;
+    int64_t bstride;               //   basis i starts at B + i * bstride
+    int count;                     // bases, one workgroup each
     int beta, tours;               // block size, tour limit
     double delta;                  // Lovasz parameter of the LLL inside
     long long max_nodes;           // enumeration nodes per block SVP
     long long max_lll_iters;       // LLL iterations over the whole run
-    int *out;                      // [0] status (0, -4 overflow, -10 iteration cap), [1] insertions
-    long long *nodes;              // [0] SVP nodes
+    int *out;                      // per basis i: [2i] status (0, -4 overflow, -10 iteration cap),
+                                   //   [2i+1] insertions
+    long long *nodes;              // per basis: SVP nodes
     int b_in_lds;                  // set by launch_bkz: the basis fits in LDS
 };
 hipError_t launch_bkz(BkzArgs a, hipStream_t st);
+
+// Shuffled instance copies (restart.hip): out[r] = A[:, perm[r]] (copies x m x n);
+// x[s][perm[j]] = xc[s][j] for s < rows.
+hipError_t launch_permute_cols(const int32_t *A, int m, int n, const int32_t *perm, int copies, int32_t *out,
+                               hipStream_t st);
+hipError_t launch_unpermute_rows(const uint8_t *xc, int64_t rows, int n, const int32_t *perm, uint8_t *x,
+                                 hipStream_t st);
 size_t bkz_lds_bytes(int k);
 
 // Per-instance fields are read as base[i * stride] (in 4-byte units), so a

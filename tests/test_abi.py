@@ -49,6 +49,8 @@ def test_strerror_and_defaults(lib):
     p = M.msp_params_default()
     assert p.N == 1024 and abs(p.delta - 0.99) < 1e-15 and p.eps == 1e-9
     assert p.split_depth == -1 and p.hoelder == 1 and p.onedir == 1
+    assert p.disc_budget == -1 and p.bkz_block == 0 and p.bkz_tours == 4
+    assert p.restarts == 1 and p.restart_seed == 1
 
 
 def test_status_codes_match_header():
