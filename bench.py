@@ -152,9 +152,16 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
             prm = M.msp_params_default(time_cap_ms=args.ttfs_cap_ms, bkz_block=args.bkz)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            Bk = M.msp_reduce(ctx, A, d, prm)
-            mode, order = orders[name]
-            r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=mode, order=order, cap=64, raise_on_error=False)
+            if name.startswith("lds-r"):
+                # "lds-r<R>[-learned]": LDS over R shuffled copies, reduced together
+                prm.restarts = int(name[5:].split("-")[0])
+                r = M.msp_solve_first(ctx, A, d, params=prm, cap=64, raise_on_error=False,
+                                      order=M.MSP_LEARNED if name.endswith("-learned") else M.MSP_PLAIN)
+            else:
+                Bk = M.msp_reduce(ctx, A, d, prm)
+                mode, order = orders[name]
+                r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=mode, order=order, cap=64,
+                                    raise_on_error=False)
             torch.cuda.synchronize()
             e2e = (time.perf_counter() - t0) * 1e3
             xs = r.x.cpu().numpy().astype(np.int64)
@@ -163,7 +170,7 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
                 raise RuntimeError("a first-mode row does not satisfy A x = d")
             st = r.stats
             row[name] = {"ttfs_ms": st["ttfs_ms"] if ok else None, "end_to_end_ms": e2e if ok else None,
-                         "censored": not ok, "status": r.status, "roots": st["roots"],
+                         "censored": not ok, "status": r.status, "roots": st["roots"], "copy": st["copy"],
                          "split_depth": st["split_depth"], "ordering_ms": st["ordering_ms"],
                          "rootgen_ms": st["rootgen_ms"], "stages": st["stages"], "root_level": st["root_level"],
                          "initial_items": st["initial_items"]}

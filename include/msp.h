@@ -241,10 +241,12 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
  * GPU).  Copy 0 is the instance as given; copy i > 0 permutes the variables by
  * a shuffle drawn from p->restart_seed and i.  All p->restarts copies are
  * reduced together (one LLL launch, then one BKZ launch when p->bkz_block >= 2,
- * one wave per copy).  The LDS passes then run by rising budget B, copy after
- * copy within each B (each pass as by msp_enumerate with MSP_LDS, in `order`),
- * and stop at the first verified hit.  The final unlimited pass runs on copy 0
- * only and is exhaustive.  x_dev receives up to `cap` rows in the caller's
+ * one wave per copy).  The LDS passes (each as by msp_enumerate with MSP_LDS,
+ * in `order`) then run in rounds q = 0, 1, 2, ...: in round q copy r runs
+ * budget q - floor(log2(r + 1)), copies in index order, so copy 0 leads and
+ * each doubling of the copy count trails by one budget.  The search stops at
+ * the first verified hit.  Once every copy has run budget min(k, 255), copy 0
+ * runs the unlimited pass, which is exhaustive.  x_dev receives up to `cap` rows in the caller's
  * variable order, *n_found their count (0 only if the instance has no
  * solution, or on MSP_E_TIMEOUT), stats the summed counters with copy and
  * copies set.  A copy whose reduction fails (e.g. MSP_E_NOT_ISOLATED) is

@@ -925,15 +925,32 @@ int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_
     acc.ttfs_ms = -1.0;
     acc.copy = -1;
     acc.copies = nok;
-    // ---- LDS passes by rising budget, copy after copy within each budget ----
+    // ---- LDS passes in rounds: in round q copy r runs budget q - lag(r) ----
+    // lag(r) = floor(log2(r + 1)): copy 0 leads, and each doubling of the
+    // copy count trails by one budget.  A pass costs a few times the pass one
+    // budget lower, so a round costs about two passes of copy 0 while every
+    // copy still advances.  After every copy has run budget maxb, copy 0 runs
+    // the unlimited, exhaustive pass.
     const auto ts = std::chrono::steady_clock::now();
     const int maxb = std::min(k, 255);
+    auto lag = [](int r) {
+        int l = 0;
+        while ((2 << l) <= r + 1) ++l;
+        return l;
+    };
+    const int last_round = maxb + lag(R - 1);
     int passes = 0;
     bool done = false;
-    for (int B = 0; B <= maxb + 1 && !done; ++B) {
+    for (int round = 0; round <= last_round + 1 && !done; ++round) {
         for (int r = 0; r < R && !done; ++r) {
             if (!ok[r]) continue;
-            if (B > maxb && r > 0) break;  // the unlimited pass: copy 0 only, exhaustive
+            int B = round - lag(r);
+            if (round > last_round) {
+                if (r > 0) break;  // the unlimited pass: copy 0 only, exhaustive
+                B = maxb + 1;
+            } else if (B < 0 || B > maxb) {
+                continue;
+            }
             msp_params q = p;
             q.disc_budget = B <= maxb ? B : -1;
             if (q.target_roots == 0) q.target_roots = 8 * 256 * c->num_cus;
