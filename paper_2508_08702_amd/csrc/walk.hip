@@ -150,7 +150,9 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
     }
 }
 
-template <int DIMP, int BLOCK>
+// BUDGETED: a discrepancy budget is set (a.budget >= 0); without one the
+// discrepancy bookkeeping is compiled out.
+template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
     constexpr int kInner = 32;  // iterations of the inner loop between rare-work passes
@@ -304,17 +306,17 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     double yD, lD, bD;
                     int uD;
                     if (D == t + 1) {
-                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf; dD = Pdsc;
+                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf; dD = BUDGETED ? Pdsc : 0;
                     } else {
                         const double *e = stk + (size_t)D * 4;
-                        yD = e[0]; lD = e[1]; fD = (int)e[2]; dD = (int)e[3];
+                        yD = e[0]; lD = e[1]; fD = (int)e[2]; dD = BUDGETED ? (int)e[3] : 0;
                         bD = s_beta[D];
                         uD = my_u[k - 1 - D];
                     }
                     const int odD = fD & F_ONEDIR, drD = (fD & F_DIRPOS) ? 1 : -1;
                     const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
                     un = odD ? uD + drD : zig_next(zD, uD);
-                    if (budget >= 0 && dD + zig_rank(zD, un, (fD & F_TZ) != 0) > budget) {
+                    if (BUDGETED && dD + zig_rank(zD, un, (fD & F_TZ) != 0) > budget) {
                         // the budget ends level D before its next value
                         top = D - 1;
                         cand = false;
@@ -419,7 +421,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 t = T;
                 top = T;
                 tz = (mt.z & F_TZ) ? 1 : 0;
-                dsc = mt.w;
+                if (BUDGETED) dsc = mt.w;
                 bt = s_beta[T];
                 enter_level();
                 if (!(mt.z & F_FRESH)) {
@@ -448,7 +450,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             while (state == RUN) {
                 // a discrepancy budget ends the level at the first value whose
                 // rank takes the path beyond it
-                if (!fex && budget >= 0 && dsc + zig_rank(z, u, tz != 0) > budget) fex = 1;
+                if (BUDGETED && !fex && dsc + zig_rank(z, u, tz != 0) > budget) fex = 1;
                 if (!fex) {
                     const double x = add_rn((double)u, y);
                     const double l = partial_norm(x, bt, lpar);
@@ -493,7 +495,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 lpar = Pl;
                 bt = Pbt;
                 u = Pu;
-                dsc = Pdsc;
+                if (BUDGETED) dsc = Pdsc;
                 onedir = Pf & F_ONEDIR;
                 dir = (Pf & F_DIRPOS) ? 1 : -1;
                 tz = (Pf & F_TZ) ? 1 : 0;
@@ -505,7 +507,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     Py = e[0];
                     Pl = e[1];
                     Pf = (int)e[2];
-                    Pdsc = (int)e[3];
+                    if (BUDGETED) Pdsc = (int)e[3];
                     Pbt = s_beta[t + 1];
                     Pu = my_u[k - 2 - t];
                     Pdirty = 0;
@@ -556,11 +558,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                             e[0] = Py;
                             e[1] = Pl;
                             e[2] = (double)Pf;
-                            e[3] = (double)Pdsc;
+                            if (BUDGETED) e[3] = (double)Pdsc;
                         }
                         Pdirty = 1;
-                        Pdsc = dsc;
-                        dsc += zig_rank(z, u, tz != 0);
+                        if (BUDGETED) {
+                            Pdsc = dsc;
+                            dsc += zig_rank(z, u, tz != 0);
+                        }
                         Py = y;
                         Pl = lpar;
                         Pbt = bt;
@@ -606,15 +610,21 @@ hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const 
 
 int walk_muc_len(int k) { return walk_muc_offset(k, k - 1) + 8; }
 
+template <int DIMP, int BLOCK, bool BUDGETED>
+static hipError_t launch_variant(const WalkArgs &a, int num_cus, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)walk_kernel<DIMP, BLOCK, BUDGETED>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((walk_kernel<DIMP, BLOCK, BUDGETED>), dim3(num_cus), dim3(BLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
 template <int DIMP, int BLOCK>
 static hipError_t launch_one(const WalkArgs &a, int num_cus, hipStream_t st) {
     const size_t lds = walk_lds_bytes(DIMP, BLOCK, a.k, a.L, a.muc_len);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)walk_kernel<DIMP, BLOCK>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((walk_kernel<DIMP, BLOCK>), dim3(num_cus), dim3(BLOCK), lds, st, a);
-    return hipGetLastError();
+    return a.budget >= 0 ? launch_variant<DIMP, BLOCK, true>(a, num_cus, lds, st)
+                         : launch_variant<DIMP, BLOCK, false>(a, num_cus, lds, st);
 }
 
 int walk_max_level(int dimp, int k) {
