@@ -40,8 +40,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scale factors from a 1 GiB copy in the
 # same run), valid only for the kernel source they were taken on.
 WALK_TRAFFIC = {
-    "m9-1": {"bytes": 3.464e12,
-             "sha256": "69514037192956dd9320dafc06049f990db41c5b678130456273e412204b8921",
+    "m9-1": {"bytes": 3.479e12,
+             "sha256": "cd385812b38cb41c994ee864603c1f16086a4518b4466870704f1df5dc8ad74d",
              "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
 }
 
