@@ -170,10 +170,12 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
                 raise RuntimeError("a first-mode row does not satisfy A x = d")
             st = r.stats
             row[name] = {"ttfs_ms": st["ttfs_ms"] if ok else None, "end_to_end_ms": e2e if ok else None,
-                         "censored": not ok, "status": r.status, "roots": st["roots"], "copy": st["copy"],
+                         "censored": not ok, "status": r.status, "roots": st["roots"],
                          "split_depth": st["split_depth"], "ordering_ms": st["ordering_ms"],
                          "rootgen_ms": st["rootgen_ms"], "stages": st["stages"], "root_level": st["root_level"],
                          "initial_items": st["initial_items"]}
+            if name.startswith("lds-r"):
+                row[name]["copy"] = st["copy"]
         print(json.dumps({"ttfs_instance": row}), file=sys.stderr, flush=True)
         per.append(row)
 
