@@ -235,7 +235,7 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
                     const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
                     int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
 
-/* A first solution from A and d alone, by limited discrepancy search over
+/* A first binary solution from A and d alone, by limited discrepancy search over
  * randomly shuffled copies of the instance (Section 4 proposes running the
  * method on randomly reordered input bases at once; here the copies share one
  * GPU).  Copy 0 is the instance as given; copy i > 0 permutes the variables by

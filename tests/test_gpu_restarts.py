@@ -82,6 +82,28 @@ def test_shuffled_copies_return_oracle_solutions(M, ctx, bkz):
     assert any(h > 0 for h in hits)      # rows found on shuffled copies came back in the given order
 
 
+def test_learned_roots_on_reduced_copies(M, ctx):
+    M.msp_model_init(ctx, 8)
+    for m, D, seed in ((6, 100, 2000), (7, 200, 4102)):
+        inst = mi.msp_class(m, D, seed)
+        sols = _oracle_set(inst)
+        prm = M.msp_params_default(time_cap_ms=60000.0, restarts=6, restart_seed=3, bkz_block=12)
+        r = M.msp_solve_first(ctx, _dev(inst.A), _dev(inst.d), order=M.MSP_LEARNED, params=prm)
+        assert r.status == M.MSP_OK and r.n_found >= 1 and r.stats["copies"] == 6
+        assert {tuple(x) for x in r.x.cpu().numpy()} <= sols
+        assert r.stats["ordering_ms"] > 0.0
+
+
+def test_time_cap_ends_the_search(M, ctx):
+    # an m=9 instance needs far more than 1 ms of search: the cap is reached
+    inst = mi.msp_class(9, 100, 4504)
+    prm = M.msp_params_default(time_cap_ms=1.0, restarts=4)
+    r = M.msp_solve_first(ctx, _dev(inst.A), _dev(inst.d), params=prm)
+    assert r.status == M.MSP_E_TIMEOUT
+    if r.n_found:
+        assert E.verify(inst.A, inst.d, r.x.cpu().numpy())
+
+
 def test_infeasible_instance_ends_exhaustive(M, ctx):
     inst = mi.cornuejols_dawande(6, 31)
     d_np = inst.d.copy()
