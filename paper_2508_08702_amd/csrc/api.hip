@@ -701,12 +701,12 @@ static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int6
         acc.rootgen_ms += st.rootgen_ms;
         acc.ordering_ms += st.ordering_ms;
         acc.kernel_ms += st.kernel_ms;
-        if (rc != MSP_OK) break;
-        if (*n_found > 0) {
+        if (*n_found > 0) {  // also with MSP_E_CAPACITY or MSP_E_TIMEOUT: the rows are valid
             // host time of the earlier passes, then this pass up to its hit
             acc.ttfs_ms = before + (st.ttfs_ms >= 0.0 ? st.ttfs_ms + st.gs_ms + st.rootgen_ms : st.total_ms);
             break;
         }
+        if (rc != MSP_OK) break;
         if (B > maxb) break;  // the unlimited walk found nothing: no solution
     }
     acc.stages = passes;
@@ -985,10 +985,8 @@ int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_
             acc.rootgen_ms += sti.rootgen_ms;
             acc.ordering_ms += sti.ordering_ms;
             acc.kernel_ms += sti.kernel_ms;
-            if (rc != MSP_OK) {
-                done = true;
-                break;
-            }
+            // a hit counts also when the pass ends with MSP_E_CAPACITY (more
+            // hits than cap rows) or MSP_E_TIMEOUT: its rows are valid
             if (nf > 0) {
                 if (r > 0 && cap > 0) {
                     MSP_TRY(launch_unpermute_rows(c->rs_x.as<uint8_t>(), std::min(nf, cap), n,
@@ -1001,6 +999,7 @@ int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_
                     before + (sti.ttfs_ms >= 0.0 ? sti.ttfs_ms + sti.gs_ms + sti.rootgen_ms : sti.total_ms);
                 done = true;
             }
+            if (rc != MSP_OK) done = true;
         }
     }
     acc.stages = passes;

@@ -82,6 +82,26 @@ def test_shuffled_copies_return_oracle_solutions(M, ctx, bkz):
     assert any(h > 0 for h in hits)      # rows found on shuffled copies came back in the given order
 
 
+def test_one_row_capacity_keeps_the_hit(M, ctx):
+    # several lanes can hit in the same pass: with room for one row the call
+    # may report MSP_E_CAPACITY, and the row it returns is still a solution
+    inst = mi.msp_class(5, 50, 1)
+    sols = _oracle_set(inst)
+    for R, rs in ((1, 1), (8, 5), (8, 9)):
+        prm = M.msp_params_default(time_cap_ms=60000.0, restarts=R, restart_seed=rs)
+        r = M.msp_solve_first(ctx, _dev(inst.A), _dev(inst.d), params=prm, cap=1)
+        assert r.status in (M.MSP_OK, M.MSP_E_CAPACITY) and r.n_found >= 1
+        x = r.x.cpu().numpy()
+        assert x.shape[0] == 1 and tuple(x[0]) in sols
+        assert (r.status == M.MSP_E_CAPACITY) == (r.n_found > 1)
+        assert r.stats["copy"] >= 0 and r.stats["ttfs_ms"] > 0.0
+    A, d = _dev(inst.A), _dev(inst.d)
+    q = M.msp_enumerate(ctx, A, d, M.msp_reduce(ctx, A, d), params=M.msp_params_default(time_cap_ms=60000.0),
+                        mode=M.MSP_LDS, cap=1)
+    assert q.status in (M.MSP_OK, M.MSP_E_CAPACITY) and q.n_found >= 1 and q.stats["ttfs_ms"] > 0.0
+    assert tuple(q.x.cpu().numpy()[0]) in sols
+
+
 def test_learned_roots_on_reduced_copies(M, ctx):
     M.msp_model_init(ctx, 8)
     for m, D, seed in ((6, 100, 2000), (7, 200, 4102)):
