@@ -198,7 +198,7 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the walk runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
