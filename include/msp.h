@@ -249,7 +249,8 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
  * runs the unlimited pass, which is exhaustive.  x_dev receives up to `cap` rows in the caller's
  * variable order, *n_found their count (0 only if the instance has no
  * solution, or on MSP_E_TIMEOUT), stats the summed counters with copy and
- * copies set.  A copy whose reduction fails (e.g. MSP_E_NOT_ISOLATED) is
+ * copies set; there reduce_ms is the reduction of all copies and ttfs_ms runs
+ * from the start of the call to the first verified hit (reduction included).  A copy whose reduction fails (e.g. MSP_E_NOT_ISOLATED) is
  * skipped; the call fails with that status only if copy 0 fails.
  * p->time_cap_ms bounds the search after the reduction.
  * Errors: those of msp_reduce and msp_enumerate; MSP_E_ARG for restarts
