@@ -235,8 +235,8 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
                     const int64_t *d_dev, int mode, int order, const msp_params *p, uint8_t *x_dev,
                     int64_t *n_found, int32_t *status, msp_stats *stats, void *stream);
 
-/* A first binary solution from A and d alone, by limited discrepancy search over
- * randomly shuffled copies of the instance (Section 4 proposes running the
+/* A first binary solution from A and d alone, by limited discrepancy search
+ * over randomly shuffled copies of the instance (Section 4 proposes running the
  * method on randomly reordered input bases at once; here the copies share one
  * GPU).  Copy 0 is the instance as given; copy i > 0 permutes the variables by
  * a shuffle drawn from p->restart_seed and i.  All p->restarts copies are
@@ -246,13 +246,15 @@ int msp_solve_batch(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const i
  * budget q - floor(log2(r + 1)), copies in index order, so copy 0 leads and
  * each doubling of the copy count trails by one budget.  The search stops at
  * the first verified hit.  Once every copy has run budget min(k, 255), copy 0
- * runs the unlimited pass, which is exhaustive.  x_dev receives up to `cap` rows in the caller's
- * variable order, *n_found their count (0 only if the instance has no
- * solution, or on MSP_E_TIMEOUT), stats the summed counters with copy and
- * copies set; there reduce_ms is the reduction of all copies and ttfs_ms runs
- * from the start of the call to the first verified hit (reduction included).  A copy whose reduction fails (e.g. MSP_E_NOT_ISOLATED) is
- * skipped; the call fails with that status only if copy 0 fails.
- * p->time_cap_ms bounds the search after the reduction.
+ * runs the unlimited pass, which is exhaustive.
+ * x_dev receives up to `cap` rows in the caller's variable order, *n_found
+ * their count (0 only if the instance has no solution, or on MSP_E_TIMEOUT).
+ * stats holds the summed counters with copy and copies set; its reduce_ms is
+ * the reduction of all copies, and its ttfs_ms runs from the start of the call
+ * to the first verified hit (reduction included).  A copy whose reduction
+ * fails (e.g. MSP_E_NOT_ISOLATED) is skipped; the call fails with that status
+ * only if copy 0 fails.  p->time_cap_ms bounds the search after the
+ * reduction.
  * Errors: those of msp_reduce and msp_enumerate; MSP_E_ARG for restarts
  * outside 1..64. */
 int msp_solve_first(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev, int order,
