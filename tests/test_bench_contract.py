@@ -1,0 +1,31 @@
+"""bench.py host-side contract: more than one GPU is refused with a message,
+and the HBM traffic figure it reports comes from a committed profile of the
+same walk-kernel source (its hash and byte count are written there)."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_traffic_figure_matches_its_profile():
+    import bench
+    for workload, tr in bench.WALK_TRAFFIC.items():
+        assert workload in bench.WORKLOADS
+        path = os.path.join(ROOT, tr["profile"])
+        txt = open(path).read()
+        assert tr["sha256"] in txt
+        # the profile states the per-launch bytes that bench.py reports
+        assert f"{tr['bytes']:.3e}".replace("e+", "e") in txt.replace("e+", "e")
