@@ -44,8 +44,9 @@ extern "C" {
 enum {
     MSP_OK = 0,
     MSP_E_ARG = -1,          /* bad shape, null pointer, m > n, n > MSP_MAX_N     */
-    MSP_E_RANK = -2,         /* fewer than n-m+1 kernel vectors: rank A < m        */
-    MSP_E_NOT_ISOLATED = -3, /* N too small: reduced basis does not split (Sec. 2) */
+    MSP_E_RANK = -2,         /* more than n-m+1 zero-top vectors: rank A < m       */
+    MSP_E_NOT_ISOLATED = -3, /* fewer than n-m+1 zero-top vectors: N too small,
+                                the reduced basis does not split (Sec. 2)         */
     MSP_E_OVERFLOW = -4,     /* an integer bound was exceeded (see each call)      */
     MSP_E_CAPACITY = -5,     /* more solutions than `cap`; *n_found = true total   */
     MSP_E_TIMEOUT = -6,      /* time cap hit; partial results are valid            */

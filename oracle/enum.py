@@ -36,7 +36,7 @@ class _Args(C.Structure):
         ("cap", C.c_int64), ("time_cap_s", C.c_double),
         ("sol", C.c_void_p), ("n_found", C.c_void_p), ("counters", C.c_void_p),
         ("level_counts", C.c_void_p), ("n_roots", C.c_void_p), ("timed_out", C.c_void_p),
-        ("cvec", C.c_void_p), ("disc_budget", C.c_int),
+        ("cvec", C.c_void_p), ("disc_budget", C.c_int), ("disc_count", C.c_int),
     ]
 
 
@@ -82,7 +82,8 @@ def sort_rows(x: np.ndarray) -> np.ndarray:
 def enumerate_prepared(P: lattice.Prepared, *, split: int = 0, threads: int = 1,
                        mode: str = "all", cap: int = 1 << 16, hoelder: bool = True,
                        onedir: bool = True, eps: float = EPS, time_cap_s: float = 0.0,
-                       level_counts: bool = False, disc_budget: int = -1) -> Result:
+                       level_counts: bool = False, disc_budget: int = -1,
+                       disc_count: bool = False) -> Result:
     """Enumerate every v in the kernel lattice with ||v||_inf <= r_max and
     v_n = r_max (each solution once) on the basis held by ``P`` (binary:
     r_max = 1)."""
@@ -110,6 +111,7 @@ def enumerate_prepared(P: lattice.Prepared, *, split: int = 0, threads: int = 1,
     cvec = None if P.cvec is None else np.ascontiguousarray(P.cvec, dtype=np.int64)
     a.cvec = cvec.ctypes.data if cvec is not None else None
     a.disc_budget = int(disc_budget)
+    a.disc_count = int(bool(disc_count))
     a.hoelder = int(hoelder)
     a.onedir = int(onedir)
     a.mode = 1 if mode == "first" else 0

@@ -12,7 +12,7 @@
  *
  * The level-t step (Section 2, "First/Second pruning condition", Alg. 1):
  *   y_t  = sum_{i>t} u_i mu_{i,t}          centre of level t is c = -y_t,
- *                                          in the fixed order of centre() below
+ *                                          one running sum, i = t+1 .. k-1
  *   x    = u_t + y_t
  *   l    = x^2 beta_t + l'                 ||w^(t)||^2 by the recurrence
  *   prune (return) when l > R (1 + eps)    R = (n+1) r_max^2
@@ -30,10 +30,9 @@
  *   - the sign symmetry v <-> -v is broken: while every u_i above t is 0,
  *     only u_t = 0, 1, 2, ... is tried, and the first Hoelder failure there
  *     ends the level (its mirror image fails as well);
- *   - the centre sum has a fixed order: with p = k-1-i (p = 0 for the top
- *     level), term p goes to partial sum s_(p mod 8), each partial sum is
- *     accumulated from the top level down starting at 0, and
- *     y = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+ *   - the centre y_t is one running sum over i = t+1, t+2, ..., k-1 starting
+ *     at 0.0, in the index order Algorithm 1 writes it, every product and
+ *     sum rounded on its own;
  *   - eps = 1e-9 relative slack on both tests (solutions lie exactly on the
  *     l2 bound);
  *   - the r_max coordinate is the last one (index n): a solution has
@@ -80,9 +79,11 @@ typedef struct {
     int *timed_out;
     const int64_t *cvec;    /* n, c_j = r_max / r_j for bounded variables;
                              * NULL: binary (r_max = c_j = 1)                 */
-    int disc_budget;        /* limited discrepancy search: the ranks of a
-                             * path's values in their levels' value orders
-                             * sum to at most this; < 0: no limit             */
+    int disc_budget;        /* limited discrepancy search: the discrepancies
+                             * of a path sum to at most this; < 0: no limit   */
+    int disc_count;         /* 0: a value's discrepancy is its rank in the
+                             * level's value order; 1: it is 1 for every value
+                             * but the level's first (a count of departures) */
 } orc_args;
 
 /* Subtree roots, stored flat: root r has prefix u[r*k + i] (i >= level),
@@ -206,15 +207,13 @@ static int zig_next(int o, int s) {
     return -o + s;
 }
 
-/* Centre sum y_t = sum_{i>t} u_i mu_{i,t} in the order stated above. */
+/* Centre sum y_t = sum_{i=t+1}^{k-1} u_i mu_{i,t} (Algorithm 1), one running
+ * sum in that index order. */
 static double centre(const orc_args *a, const int *u, int t) {
     const int k = a->k;
-    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = k - 1; i > t; --i) {
-        const int p = k - 1 - i;
-        s[p % 8] = s[p % 8] + (double)u[i] * a->mu[(int64_t)i * k + t];
-    }
-    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    double y = 0.0;
+    for (int i = t + 1; i < k; ++i) y = y + (double)u[i] * a->mu[(int64_t)i * k + t];
+    return y;
 }
 
 /* Rank of u in its level's value order (Section 3, limited discrepancy
@@ -232,9 +231,12 @@ static int zig_rank(int u, int u1, int s, int topzero) {
     return ((o > 0) == (s > 0)) ? 2 * ao - 1 : 2 * ao;
 }
 
-/* dsc: discrepancies on the path above level t, the sum of the ranks of its
- * values.  With a budget, a level stops at the first value whose rank would
- * take the path beyond it; every later value of the level ranks higher. */
+/* dsc: discrepancies on the path above level t.  A value costs its rank
+ * (reading "rank") or 1 for any value but the first of the level (reading
+ * "count", the number of departures from the heuristic's choice).  With a
+ * budget, a level stops at the first value whose cost would take the path
+ * beyond it; under either reading every later value of the level costs at
+ * least as much. */
 static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, int topzero, int dsc) {
     const orc_args *a = W->a;
     const int dim = a->dim;
@@ -253,7 +255,8 @@ static void enum_level(orc_walker *W, int t, const double *wpar, double lpar, in
     int u = u1;
     for (;;) {
         if (g_sh->stop) { W->u[t] = 0; return; }
-        const int rank = zig_rank(u, u1, s, topzero);
+        const int r0 = zig_rank(u, u1, s, topzero);
+        const int rank = a->disc_count ? (r0 > 0) : r0;
         if (a->disc_budget >= 0 && dsc + rank > a->disc_budget) break;
         const double x = (double)u + y;
         const double l = x * x * a->beta[t] + lpar;

@@ -32,12 +32,15 @@ DEFAULT_N = 1 << 10  # Section 2: N = 2^10 suffices for the market split classes
 
 
 class NotIsolated(Exception):
-    """N was too small: the reduced basis does not split into kernel vectors
-    (zero in the first m entries) and others the way Section 2 describes."""
+    """N was too small: fewer than n - m + 1 reduced vectors are zero in their
+    first m entries, so the basis does not split into kernel vectors and
+    others the way Section 2 describes."""
 
 
 class RankDeficient(Exception):
-    """Fewer than n - rank(A) + 1 kernel vectors: the rows of A are dependent."""
+    """More than n - m + 1 reduced vectors are zero in their first m entries:
+    the kernel has dimension n - rank(A) + 1 > n - m + 1, i.e. the rows of A
+    are dependent (rank A < m)."""
 
 
 def bounds_scale(r) -> tuple[int, list[int]]:
@@ -160,14 +163,17 @@ def extract_kernel(reduced: list[list[int]], m: int) -> list[list[int]]:
 
     Exactly n - m + 1 such vectors must exist (Section 2); they then form a
     basis of the kernel of A x - d x_{n+1} = 0 (restricted to the lattice).
-    Fewer means N did not isolate the kernel (or A is rank deficient).
+    Fewer means N did not isolate the kernel; more means the kernel is larger
+    than n - m + 1, because A has dependent rows.
     """
     nv = len(reduced)
     n = nv - 1
     k_expected = n - m + 1
     kern = [v[m:] for v in reduced if all(c == 0 for c in v[:m])]
-    if len(kern) != k_expected:
+    if len(kern) < k_expected:
         raise NotIsolated(f"{len(kern)} zero-top vectors, expected {k_expected}")
+    if len(kern) > k_expected:
+        raise RankDeficient(f"{len(kern)} zero-top vectors, expected {k_expected}")
     return kern
 
 

@@ -14,7 +14,7 @@ Root features (a project addition for ordering the roots; the definitions
 below are the specification, written out in FP64 and stored as float32):
 for root r at level L with prefix u_{k-1..L}, partial norm l and projected
 vector w, R = n + 1, and per level j the centre y_j = sum_{i>j} u_i mu_{i,j}
-(the enumerator's fixed summation order) and the zig-zag rank of u_j (its index in the sequence
+(one running sum over i = j+1 .. k-1) and the zig-zag rank of u_j (its index in the sequence
 u1, u1+s, u1-s, u1+2s, ... of next(), or u_j itself while every higher u is
 zero):
     0 l/R            1 l/||w||_1 (0 if w = 0)   2 min(||w||_inf, 4)/4
@@ -47,15 +47,12 @@ class Root:
 
 
 def centre(P, u, t: int) -> float:
-    """y_t = sum_{i>t} u_i mu_{i,t} in the fixed order of the enumerator:
-    term p = k-1-i goes to partial sum s[p mod 8], each accumulated from the
-    top level down from 0.0; y = ((s0+s1)+(s2+s3)) + ((s4+s5)+(s6+s7))."""
-    k = P.k
-    s = [0.0] * 8
-    for i in range(k - 1, t, -1):
-        p = k - 1 - i
-        s[p % 8] = s[p % 8] + float(u[i]) * float(P.mu[i, t])
-    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))
+    """y_t = sum_{i=t+1}^{k-1} u_i mu_{i,t} (Algorithm 1) as one running sum in
+    that index order, starting at 0.0."""
+    y = 0.0
+    for i in range(t + 1, P.k):
+        y = y + float(u[i]) * float(P.mu[i, t])
+    return y
 
 
 def _zig_next(off: int, s: int) -> int:

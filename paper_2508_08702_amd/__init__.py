@@ -184,6 +184,61 @@ def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, device: torch.device, name: st
     return t.data_ptr()
 
 
+# Shape checks, done before any pointer reaches the library: the kernels
+# trust the sizes they are given, so a tensor smaller than its stated shape
+# would be read or written out of bounds on the device.
+
+def _shape_of(t, name: str) -> tuple:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    return tuple(t.shape)
+
+
+def _check_instance(A, d) -> tuple[int, int]:
+    """A is m x n, d holds m entries; returns (m, n)."""
+    sa = _shape_of(A, "A")
+    if len(sa) != 2 or sa[0] < 1 or sa[1] < 1:
+        raise ValueError(f"A must be a non-empty m x n matrix, got shape {sa}")
+    m, n = sa
+    sd = _shape_of(d, "d")
+    if len(sd) != 1 or sd[0] != m:
+        raise ValueError(f"d must hold m = {m} entries, got shape {sd}")
+    return m, n
+
+
+def _check_basis(basis, m: int, n: int) -> int:
+    """A kernel basis has n - m + 1 rows of n + 1 entries; returns k."""
+    sb = _shape_of(basis, "basis")
+    if len(sb) != 2 or sb != (n - m + 1, n + 1):
+        raise ValueError(f"basis must have shape ({n - m + 1}, {n + 1}), got {sb}")
+    return sb[0]
+
+
+def _check_out(out, n: int, name: str = "out") -> int:
+    """An output buffer holds rows of n bytes; returns its row count."""
+    so = _shape_of(out, name)
+    if len(so) != 2 or so[1] != n:
+        raise ValueError(f"{name} must have n = {n} columns, got shape {so}")
+    return so[0]
+
+
+def _check_bounds(r, n: int) -> None:
+    sr = _shape_of(r, "r")
+    if len(sr) != 1 or sr[0] != n:
+        raise ValueError(f"r must hold n = {n} entries, got shape {sr}")
+
+
+def _check_features(feat, label=None) -> int:
+    sf = _shape_of(feat, "feat")
+    if len(sf) != 2 or sf[1] != MSP_NFEAT:
+        raise ValueError(f"feat must have {MSP_NFEAT} columns, got shape {sf}")
+    if label is not None:
+        sl = _shape_of(label, "label")
+        if len(sl) != 1 or sl[0] != sf[0]:
+            raise ValueError(f"label must hold {sf[0]} entries, got shape {sl}")
+    return sf[0]
+
+
 class Context:
     """Owns an ``msp_ctx`` (device workspace) for one device."""
 
@@ -233,7 +288,10 @@ def msp_ctx_destroy(ctx: Context) -> None:
 def msp_gram_schmidt(ctx: Context, basis: torch.Tensor):
     """FP64 Gram-Schmidt of a kernel basis (int64 k x dim on the device).
     Returns (bhat k x dim, mu k x k, beta k) as float64 device tensors."""
-    k, dim = basis.shape
+    sb = _shape_of(basis, "basis")
+    if len(sb) != 2 or sb[0] < 1 or sb[1] < sb[0]:
+        raise ValueError(f"basis must be k x dim with 1 <= k <= dim, got shape {sb}")
+    k, dim = sb
     dev = ctx.device
     bp = _dev_ptr(basis, torch.int64, dev, "basis")
     bhat = torch.empty((k, dim), dtype=torch.float64, device=dev)
@@ -249,7 +307,7 @@ def msp_gram_schmidt(ctx: Context, basis: torch.Tensor):
 def msp_reduce(ctx: Context, A: torch.Tensor, d: torch.Tensor, params: Params | None = None):
     """Embedding + LLL + kernel extraction on the GPU.  Returns the int64
     kernel basis (k x (n+1)) as a device tensor."""
-    m, n = A.shape
+    m, n = _check_instance(A, d)
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")
@@ -278,8 +336,10 @@ def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.T
 
     MSP_CAPACITY and MSP_TIMEOUT are reported in ``status`` (rows written are
     valid); other errors raise unless ``raise_on_error`` is False."""
-    m, n = A.shape
-    k = basis.shape[0]
+    m, n = _check_instance(A, d)
+    k = _check_basis(basis, m, n)
+    if out is not None:
+        cap = min(cap, _check_out(out, n))
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")
@@ -288,7 +348,6 @@ def msp_enumerate(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.T
         out = torch.zeros((max(cap, 1), n), dtype=torch.uint8, device=dev)
     else:
         _dev_ptr(out, torch.uint8, dev, "out")
-        cap = min(cap, out.shape[0])
     p = params if params is not None else msp_params_default()
     nf = C.c_int64(0)
     st = Stats()
@@ -307,7 +366,9 @@ def msp_solve_first(ctx: Context, A: torch.Tensor, d: torch.Tensor, *, order: in
     params.restarts shuffled copies reduced together (rows in the given
     variable order).  MSP_CAPACITY and MSP_TIMEOUT are reported in ``status``;
     other errors raise unless ``raise_on_error`` is False."""
-    m, n = A.shape
+    m, n = _check_instance(A, d)
+    if out is not None:
+        cap = min(cap, _check_out(out, n))
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")
@@ -315,7 +376,6 @@ def msp_solve_first(ctx: Context, A: torch.Tensor, d: torch.Tensor, *, order: in
         out = torch.zeros((max(cap, 1), n), dtype=torch.uint8, device=dev)
     else:
         _dev_ptr(out, torch.uint8, dev, "out")
-        cap = min(cap, out.shape[0])
     p = params if params is not None else msp_params_default()
     nf = C.c_int64(0)
     st = Stats()
@@ -341,6 +401,10 @@ def _pack(ctx: Context, As: list, ds: list, cap: int):
         raise ValueError("As and ds must be non-empty lists of equal length")
     dev = ctx.device
     for i, (A, d) in enumerate(zip(As, ds)):
+        try:
+            _check_instance(A, d)
+        except ValueError as e:
+            raise ValueError(f"instance {i}: {e}") from None
         _dev_ptr(A, torch.int32, dev, f"As[{i}]")
         _dev_ptr(d, torch.int64, dev, f"ds[{i}]")
     b = len(As)
@@ -412,8 +476,8 @@ class Trace:
 def msp_root_trace(ctx: Context, A: torch.Tensor, d: torch.Tensor, basis: torch.Tensor, *,
                    params: Params | None = None, cap_roots: int = 1 << 20) -> Trace:
     """Exhaustive enumeration that also returns per-root features and labels."""
-    m, n = A.shape
-    k = basis.shape[0]
+    m, n = _check_instance(A, d)
+    k = _check_basis(basis, m, n)
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")
@@ -460,9 +524,9 @@ def msp_model_get(ctx: Context):
 
 
 def msp_model_score(ctx: Context, feat: torch.Tensor) -> torch.Tensor:
+    count = _check_features(feat)
     dev = ctx.device
     fp = _dev_ptr(feat, torch.float32, dev, "feat")
-    count = feat.shape[0]
     logit = torch.empty((count,), dtype=torch.float32, device=dev)
     rc = lib().msp_model_score(ctx.handle, fp, count, logit.data_ptr(), _stream_handle(dev))
     if rc != MSP_OK:
@@ -472,6 +536,7 @@ def msp_model_score(ctx: Context, feat: torch.Tensor) -> torch.Tensor:
 
 def msp_model_grad(ctx: Context, feat: torch.Tensor, label: torch.Tensor, pos_weight: float = 1.0):
     """Returns (gradient as a float32 device tensor, loss)."""
+    _check_features(feat, label)
     dev = ctx.device
     fp = _dev_ptr(feat, torch.float32, dev, "feat")
     lp = _dev_ptr(label, torch.uint8, dev, "label")
@@ -498,6 +563,7 @@ def msp_train_params_default(**overrides) -> TrainParams:
 
 def msp_model_train(ctx: Context, feat: torch.Tensor, label: torch.Tensor, tp: TrainParams | None = None):
     """Train the context's model on (feat, label); returns the per-epoch losses."""
+    _check_features(feat, label)
     dev = ctx.device
     fp = _dev_ptr(feat, torch.float32, dev, "feat")
     lp = _dev_ptr(label, torch.uint8, dev, "label")
@@ -515,7 +581,8 @@ def msp_reduce_bounded(ctx: Context, A: torch.Tensor, d: torch.Tensor, r: torch.
                        params: Params | None = None) -> torch.Tensor:
     """Embedding with upper bounds r (int32 device tensor, 1..255) + LLL +
     kernel extraction; returns the int64 kernel basis (k x (n+1))."""
-    m, n = A.shape
+    m, n = _check_instance(A, d)
+    _check_bounds(r, n)
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")
@@ -534,8 +601,9 @@ def msp_enumerate_bounded(ctx: Context, A: torch.Tensor, d: torch.Tensor, r: tor
                           mode: int = MSP_ALL, order: int = MSP_PLAIN, params: Params | None = None,
                           cap: int = 1 << 16, raise_on_error: bool = True) -> EnumResult:
     """All (or the first) x with A x = d and 0 <= x <= r on a given kernel basis."""
-    m, n = A.shape
-    k = basis.shape[0]
+    m, n = _check_instance(A, d)
+    _check_bounds(r, n)
+    k = _check_basis(basis, m, n)
     dev = ctx.device
     ap = _dev_ptr(A, torch.int32, dev, "A")
     dp = _dev_ptr(d, torch.int64, dev, "d")

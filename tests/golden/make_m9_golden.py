@@ -55,6 +55,7 @@ def main():
         "solutions": [[int(v) for v in row] for row in r.solutions],
         "evals": r.evals, "nodes": r.nodes, "expansions": r.expansions, "leaves": r.leaves,
         "oracle_seconds": round(r.seconds, 1), "lll_seconds": round(t_lll, 1), "threads": r.threads,
+        "centre_sum": "one running sum over i = t+1 .. k-1",
     }
     path = os.path.join(HERE, f"m9_seed{args.seed}.json")
     with open(path, "w") as f:

@@ -151,6 +151,15 @@ def test_too_small_N_is_reported():
         L.prepare(inst.A, inst.d, N=1)
 
 
+def test_dependent_rows_are_reported_as_rank_deficient():
+    # a repeated row leaves rank A = m - 1: the kernel has n - m + 2 vectors
+    inst = mi.msp_class(4, 100, 3)
+    A2 = np.vstack([inst.A, inst.A[:1]]).astype(np.int32)
+    d2 = np.concatenate([inst.d, inst.d[:1]])
+    with pytest.raises(L.RankDeficient):
+        L.prepare(A2, d2)
+
+
 @pytest.mark.parametrize("seed,m,D", [(1001, 3, 100), (21, 4, 50)])
 def test_gram_schmidt_exact_invariants(seed, m, D):
     inst = mi.msp_class(m, D, seed)

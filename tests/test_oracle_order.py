@@ -132,3 +132,35 @@ def test_roots_match_recursive_enumerator_and_partition_solutions(m, D, seed, sp
         assert abs(F[r, 12] - r / len(roots)) < 1e-7
     assert np.all(F[:, 0] <= 1.0 + 1e-6) and np.all(F[:, 1] <= 1.0 + 1e-6)
     assert np.all((F[:, 4] >= 0) & (F[:, 4] <= 1))
+
+
+def test_root_features_hand_computed_fixture():
+    """All 16 root features of three hand-made roots on a k=3, n=3, m=1
+    lattice (L = 1, R = 4), each value worked out by hand from the feature
+    definitions, independently of the oracle's code."""
+    import math
+    from types import SimpleNamespace
+
+    mu = np.zeros((3, 3))
+    mu[1, 0], mu[2, 0], mu[2, 1] = 0.5, 0.25, -0.5
+    P = SimpleNamespace(k=3, dim=4, m=1, n=3, mu=mu, beta=np.array([2.0, 3.0, 4.0]))
+    roots = [
+        # u_2 = 1 (top-zero level: rank 1); y_1 = 1 * -0.5, c = 0.5, u1 = rint(0.5) = 0,
+        # s = +1 (0 - 0.5 <= 0), u_1 = 1 is u1 + 1 on the side of s: rank 1; x_L = 0.5
+        RT.Root(u=[0, 1, 1], l=3.5, w=np.array([1.0, -1.0, 0.5, 0.0])),
+        # u_2 = 2 (rank 2); y_1 = -1, c = 1, u1 = 1, s = +1, u_1 = -1 = u1 - 2: rank 4; x_L = -2
+        RT.Root(u=[0, -1, 2], l=2.0, w=np.array([0.25, 2.0, -3.0, 5.0])),
+        # both levels top-zero with value 0: every rank, value and norm is 0
+        RT.Root(u=[0, 0, 0], l=0.0, w=np.zeros(4)),
+    ]
+    want = np.array([
+        [3.5 / 4, 3.5 / 2.5, 1 / 4, 1.0, 1.0, 1 / 8, 1.0, 1.0, 1 / 4,
+         0.25 * 3 / 4, 0.5 / 2, (1 / 3) * math.log(0.5 / 4) / 8, 0.0, 0.0, 1 / 3, 1 / 16],
+        [2 / 4, 2 / 10.25, 1.0, 3.0, 1.0, 4 / 8, 1.0, 1.5, 2 / 4,
+         4 * 3 / 4, 1.0, (1 / 3) * math.log(2 / 4) / 8, 1 / 3, 3 / 4, 1 / 3, 1 / 16],
+        [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+         0.0, 0.0, 0.0, 2 / 3, 0.0, 1 / 3, 1 / 16],
+    ], dtype=np.float32)
+    got = RT.features(P, roots, 1)
+    assert got.dtype == np.float32 and got.shape == (3, RT.NFEAT)
+    np.testing.assert_array_equal(got, want)
