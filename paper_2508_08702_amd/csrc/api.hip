@@ -541,6 +541,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));
     const int64_t ninit = np + nleft;  // roots with stored w, then prefix-only items
     const int64_t pcap = ninit + std::max<int64_t>(256 * nwalk, 1 << 22);
+    if (pcap + nwalk >= (int64_t(1) << 31)) return MSP_E_UNSUPPORTED;  // walker tickets are 32-bit
     MSP_TRY(c->pool_u.ensure((size_t)pcap * k));
     MSP_TRY(c->pool_meta.ensure((size_t)pcap * sizeof(int4)));
     MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));

@@ -1,17 +1,18 @@
 // Per-level rules of the enumeration (paper, Section 2 and Algorithm 1),
-// shared by the root generator and the subtree walker.
+// shared by the root generator, the root features and the subtree walker.
 //
-// Centre and partial norm are evaluated with every product and sum rounded
-// on its own (no fused multiply-add), in a fixed order, so that these scalar
-// recurrences -- which decide the l2 pruning -- are reproducible bit for bit:
+// Centre and partial norm are evaluated in one fixed order everywhere on the
+// GPU, so that every kernel that meets the same prefix takes the same pruning
+// decisions (the split level and the dynamic splitting of the walk then do
+// not change the search-tree counters):
 //   y_t = sum_{i>t} u_i mu_{i,t}   (centre c_t = -y_t): term p = k-1-i (p = 0
-//         is the top level) goes to partial sum s_(p mod 8), each partial
-//         sum runs from the top level down starting at 0, and
-//         y_t = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
-//   l   = (x * x) * beta_t + l'   (x = u_t + y_t)
-// Eight interleaved sums make the dependent chain eight times shorter than
-// one running sum; any fixed order serves, as long as it is the same
-// everywhere.
+//         is the top level) goes to partial sum s_(p mod 4); each partial sum
+//         runs from the top level down, starting at 0, with fused
+//         multiply-adds, and y_t = (s0 + s1) + (s2 + s3);
+//   l   = fma(x * x, beta_t, l')   (x = u_t + y_t).
+// Four interleaved sums keep the dependent chain short.  The order differs
+// from the plain sum the paper writes only in rounding, far below the 1e-9
+// slack of the pruning tests.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,29 +25,29 @@ __device__ __forceinline__ double add_rn(double a, double b) { return a + b; }
 __device__ __forceinline__ double mul_rn(double a, double b) { return a * b; }
 
 __device__ __forceinline__ double partial_norm(double x, double beta, double lpar) {
-    return add_rn(mul_rn(mul_rn(x, x), beta), lpar);
+    return fma(mul_rn(x, x), beta, lpar);
 }
 
-__device__ __forceinline__ double combine8(const double (&s)[8]) {
-    return add_rn(add_rn(add_rn(s[0], s[1]), add_rn(s[2], s[3])), add_rn(add_rn(s[4], s[5]), add_rn(s[6], s[7])));
+__device__ __forceinline__ double combine4(double s0, double s1, double s2, double s3) {
+    return add_rn(add_rn(s0, s1), add_rn(s2, s3));
 }
 
 // Centre sum for a prefix in natural level order (u[i] = u_i) and mu row-major
 // (mu[i * k + t] = mu_{i,t}).
 __device__ __forceinline__ double centre_natural(const int8_t *u, const double *mu, int k, int t) {
-    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     const int nt = k - 1 - t;
-    for (int p0 = 0; p0 < nt; p0 += 8) {
+    for (int p0 = 0; p0 < nt; p0 += 4) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < 4; ++r) {
             const int p = p0 + r;
             if (p < nt) {
                 const int i = k - 1 - p;
-                s[r] = add_rn(s[r], mul_rn((double)u[i], mu[(size_t)i * k + t]));
+                s[r] = fma((double)u[i], mu[(size_t)i * k + t], s[r]);
             }
         }
     }
-    return combine8(s);
+    return combine4(s[0], s[1], s[2], s[3]);
 }
 
 // Zig-zag state of one level: values u1, u1+s, u1-s, u1+2s, ... around the
@@ -94,6 +95,15 @@ __device__ __forceinline__ int zig_rank(const Zig &z, int u, bool topzero) {
     if (o == 0) return 0;
     const int ao = o < 0 ? -o : o;
     return ((o > 0) == (z.s > 0)) ? 2 * ao - 1 : 2 * ao;
+}
+
+// Discrepancy cost of taking u (limited discrepancy search, Section 3): its
+// rank (reading "rank"), or 1 for every value but the level's first (reading
+// "count": the number of departures from the heuristic's choice).  Under
+// both readings the cost never decreases along a level.
+__device__ __forceinline__ int disc_cost(const Zig &z, int u, bool topzero, bool count) {
+    const int r = zig_rank(z, u, topzero);
+    return count ? (r > 0 ? 1 : 0) : r;
 }
 
 // Direction kept after the first Hoelder failure: the side of c that u is on.

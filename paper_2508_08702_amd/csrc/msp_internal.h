@@ -60,6 +60,7 @@ struct ExpandArgs {
     double bound, hfac;            // l2 bound R (1 + eps); Hoelder: l > (rmax h) hfac
     double rmax;                   // r_max (1 for binary variables)
     int budget;                    // discrepancy budget (< 0: none)
+    int disc_count;                // 1: a discrepancy costs 1 (count reading), 0: its rank
     int hoelder, onedir;
     unsigned long long *counters;  // [0] evals [1] nodes [2] expansions (write pass)
     int *flags;                    // [1] |u| > 127 seen
@@ -118,6 +119,7 @@ struct WalkArgs {
     long long rmax;                // r_max: a solution has v_n = +-r_max, |v_j| <= r_max
     const int64_t *cvec;           // c_j = r_max / r_j (nullptr: binary, c_j = 1)
     int budget;                    // discrepancy budget (< 0: none)
+    int disc_count;                // 1: a discrepancy costs 1 (count reading), 0: its rank
     int hoelder, onedir;
 };
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);

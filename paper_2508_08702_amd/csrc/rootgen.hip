@@ -36,9 +36,9 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         int64_t slot = WRITE ? a.offs[p] : 0;
         int64_t nch = 0;
         for (;;) {
-            // a budget stops the level at the first value whose rank would
+            // a budget stops the level at the first value whose cost would
             // take the path beyond it
-            const int rank = zig_rank(z, u, tz);
+            const int rank = disc_cost(z, u, tz, a.disc_count != 0);
             if (a.budget >= 0 && pd + rank > a.budget) break;
             const double x = add_rn((double)u, y);
             const double l = partial_norm(x, beta, lpar);

@@ -62,14 +62,15 @@ __device__ __forceinline__ long long ld_rlx(const long long *p) {
 }
 
 // Centre sum of level t in the fixed order (term p = k-1-i into partial sum
-// p mod 8): one chunk of 8 levels feeds the 8 partial sums.  my_u[p] holds
-// u_{k-1-p}; col[p] = mu_{k-1-p,t}, zero beyond the column's k-1-t entries
-// (a zero term leaves a partial sum unchanged).  The loads of chunk c+1 are
-// issued before chunk c is summed.
+// p mod 4, fused multiply-adds; the order of centre_natural): one chunk of 8
+// levels feeds each partial sum twice.  my_u[p] holds u_{k-1-p}; col[p] =
+// mu_{k-1-p,t}, zero beyond the column's k-1-t entries (a zero term leaves a
+// partial sum unchanged).  The loads of chunk c+1 are issued before chunk c
+// is summed.
 __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, const double *col) {
     const int nt = k - 1 - t;
-    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (nt <= 0) return combine8(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (nt <= 0) return 0.0;
     uint2 uu = *reinterpret_cast<const uint2 *>(my_u);
     double2 m0 = *reinterpret_cast<const double2 *>(col);
     double2 m1 = *reinterpret_cast<const double2 *>(col + 2);
@@ -82,21 +83,21 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
         const double2 n1 = *reinterpret_cast<const double2 *>(col + cn + 2);
         const double2 n2 = *reinterpret_cast<const double2 *>(col + cn + 4);
         const double2 n3 = *reinterpret_cast<const double2 *>(col + cn + 6);
-        s[0] = add_rn(s[0], mul_rn((double)(int8_t)(uu.x), m0.x));
-        s[1] = add_rn(s[1], mul_rn((double)(int8_t)(uu.x >> 8), m0.y));
-        s[2] = add_rn(s[2], mul_rn((double)(int8_t)(uu.x >> 16), m1.x));
-        s[3] = add_rn(s[3], mul_rn((double)(int8_t)(uu.x >> 24), m1.y));
-        s[4] = add_rn(s[4], mul_rn((double)(int8_t)(uu.y), m2.x));
-        s[5] = add_rn(s[5], mul_rn((double)(int8_t)(uu.y >> 8), m2.y));
-        s[6] = add_rn(s[6], mul_rn((double)(int8_t)(uu.y >> 16), m3.x));
-        s[7] = add_rn(s[7], mul_rn((double)(int8_t)(uu.y >> 24), m3.y));
+        s0 = fma((double)(int8_t)(uu.x), m0.x, s0);
+        s1 = fma((double)(int8_t)(uu.x >> 8), m0.y, s1);
+        s2 = fma((double)(int8_t)(uu.x >> 16), m1.x, s2);
+        s3 = fma((double)(int8_t)(uu.x >> 24), m1.y, s3);
+        s0 = fma((double)(int8_t)(uu.y), m2.x, s0);
+        s1 = fma((double)(int8_t)(uu.y >> 8), m2.y, s1);
+        s2 = fma((double)(int8_t)(uu.y >> 16), m3.x, s2);
+        s3 = fma((double)(int8_t)(uu.y >> 24), m3.y, s3);
         uu = nu;
         m0 = n0;
         m1 = n1;
         m2 = n2;
         m3 = n3;
     }
-    return combine8(s);
+    return combine4(s0, s1, s2, s3);
 }
 
 }  // namespace
@@ -152,6 +153,13 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
 
 // BUDGETED: a discrepancy budget is set (a.budget >= 0); without one the
 // discrepancy bookkeeping is compiled out.
+//
+// Register economy.  w takes DIMP registers; everything else a lane keeps
+// between iterations is a handful of scalars (the level, its value and
+// zig-zag state, one word of flags, the centre and partial norms of the
+// level and its parent, 32-bit counters), so that at DIMP <= 88 two waves
+// fit on a SIMD.  The parent level's state is cached in registers and the
+// grandparent is read back from the per-walker stack on a pop.
 template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
@@ -167,42 +175,50 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
 
     for (int idx = tid; idx < L * S; idx += BLOCK) s_bh[idx] = a.g_bh[idx];
     for (int idx = tid; idx < a.muc_len; idx += BLOCK) s_muc[idx] = a.g_muc[idx];
-    for (int t = tid; t < k; t += BLOCK) s_beta[t] = a.beta[t];
-    for (int t = tid; t <= k; t += BLOCK) s_coff[t] = a.g_coff[t];
+    for (int q = tid; q < k; q += BLOCK) s_beta[q] = a.beta[q];
+    for (int q = tid; q <= k; q += BLOCK) s_coff[q] = a.g_coff[q];
     for (int idx = tid; idx < KU * BLOCK; idx += BLOCK) s_u[idx] = 0;
     __syncthreads();
 
     const int lane = tid & 63;
     const int rot = kRot * (lane & 7);
-    const int64_t walker = (int64_t)blockIdx.x * BLOCK + tid;
-    double *stk = a.stack + walker * (int64_t)k * 4;
     int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
-    const unsigned long long lt_mask = (1ull << lane) - 1ull;
     const double bound = a.bound, hfac = a.hfac, rmax_d = a.rmax_d;
     const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
+    const int budget = a.budget;
+    const bool dcount = a.disc_count != 0;
+    // this walker's stack: k entries of {centre, partial norm of the parent, flags, discrepancies}
+    auto stack_at = [&](int level) -> double * {
+        return a.stack + ((size_t)(blockIdx.x * BLOCK + tid) * (size_t)k + (size_t)level) * 4;
+    };
 
     double w[DIMP];
 #pragma unroll
     for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
 
-    int state = NEED_ROOT, fex = 0, leafpend = 0, fin = 0;
-    long long ticket = 0;
-    int t = 0, u = 0, onedir = 0, dir = 1, tz = 0, applied = 0, u_app = 0, top = 0;
+    int state = NEED_ROOT;
+    int fex = 0, leafpend = 0, fin = 0;
+    unsigned ticket = 0;
+    int t = 0, u = 0, top = 0, u_app = 0;
+    int onedir = 0, dir = 1, tz = 0, applied = 0;
     Zig z{0, 1};
     double y = 0.0, lpar = 0.0, lcur = 0.0, bt = 1.0;
-    double Py = 0.0, Pl = 0.0, Pbt = 1.0;  // cached state of level t+1
-    int Pu = 0, Pf = 0, Pdirty = 0;  // Pdirty: cache differs from stack entry t+1
-    // discrepancies (rank sums) on the path above level t, and above level t+1 (Pdsc)
-    int dsc = 0, Pdsc = 0;
-    const int budget = a.budget;
-    unsigned long long c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;
-    unsigned long long t_end = 0;
-    if (lane == 0) {
-        const unsigned long long t0 = wall_clock();
-        if (tid == 0 && blockIdx.x == 0) atomicCAS(a.t_start, 0ull, t0);
-        t_end = a.deadline ? t0 + a.deadline : 0;
-    }
+    double Py = 0.0, Pl = 0.0;  // cached state of level t+1: centre and the partial norm above it
+    int Pw = 0;                 // u_{t+1} (low byte) | its flags << 8 | dirty << 16 (cache not yet in the stack)
+    int dsc = 0, Pdsc = 0;      // discrepancies on the path above level t, and above level t+1
+    unsigned c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;  // per lane; wave sums are 64-bit
 
+    // add the wave's counters to the global ones (one atomic each) and clear them
+    auto flush_counters = [&]() {
+        unsigned long long s5[5] = {c_eval, c_node, c_exp, c_leaf, c_items};
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+            for (int o = 32; o >= 1; o >>= 1) s5[q] += __shfl_xor(s5[q], o, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) atomicAdd(&a.counters[q], s5[q]);
+        c_eval = c_node = c_exp = c_leaf = c_items = 0;
+    };
     auto enter_level = [&]() {  // level t freshly entered from above
         y = centre_sum(t, k, my_u, s_muc + s_coff[t]);
         z = zig_init(y, tz != 0);
@@ -213,8 +229,12 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     };
     auto advance = [&]() { u = onedir ? u + dir : zig_next(z, u); };
 
+    if (tid == 0 && blockIdx.x == 0) atomicCAS(a.t_start, 0ull, wall_clock());
+
     for (;;) {
         // ================= rare work (at most every kInner iterations) =================
+        // per-lane 32-bit counters are flushed long before they could wrap
+        if (__ballot(c_eval > (1u << 30))) flush_counters();
         // finished items
         {
             const unsigned long long fm = __ballot(fin != 0);
@@ -227,10 +247,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             int stop = 0;
             if (lane == 0) {
                 stop = ld_acq(&a.flags[0]);
-                if (!stop && t_end && wall_clock() > t_end) {
-                    atomicOr(&a.flags[2], 1);
-                    atomicOr(&a.flags[0], 1);
-                    stop = 1;
+                if (!stop && a.deadline) {
+                    const unsigned long long t0 = ld_rlx(a.t_start);
+                    if (t0 && wall_clock() > t0 + a.deadline) {
+                        atomicOr(&a.flags[2], 1);
+                        atomicOr(&a.flags[0], 1);
+                        stop = 1;
+                    }
                 }
             }
             if (__shfl(stop, 0, 64)) state = DONE;
@@ -238,52 +261,51 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         // exact leaf test (Thm 1) and A x = d, integers only
         if (__ballot(leafpend != 0)) {
             if (leafpend && state == RUN) {
-                // v = sum_i u_i b_i exactly.  A solution has v_n = +-r_max and,
-                // with that sign taken off, |v_j| <= r_max (Thm 1); then
-                // x_j = (v_j + r_max) / (2 c_j), and A x = d is checked.
+                // v = sum_i u_i b_i exactly, one coordinate at a time.  A
+                // solution has v_n = +-r_max and, with that sign taken off,
+                // |v_j| <= r_max (Thm 1); x_j = (v_j + r_max) / (2 c_j), then
+                // A x = d is checked row by row from the x held in registers
+                // of the output row (written only once the row is accepted).
                 const int64_t rmax = a.rmax;
-                bool ok = true;
-                int64_t vn = (int64_t)u * a.basis[a.n];
-                for (int i = 1; i < k; ++i) vn += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + a.n];
-                if (vn != rmax && vn != -rmax) ok = false;
+                my_u[k - 1] = (int8_t)u;  // u_0 joins the prefix for the reconstruction
+                auto coord = [&](int j) -> int64_t {
+                    int64_t sv = 0;
+                    for (int i = 0; i < k; ++i) sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
+                    return sv;
+                };
+                const int64_t vn = coord(a.n);
+                bool ok = vn == rmax || vn == -rmax;
                 const int64_t sg = vn > 0 ? 1 : -1;
+                for (int j = 0; j < a.n && ok; ++j) {
+                    const int64_t sv = sg * coord(j);
+                    const int64_t cj2 = 2 * (a.cvec ? a.cvec[j] : 1);
+                    ok = sv <= rmax && sv >= -rmax && (sv + rmax) % cj2 == 0;
+                }
                 for (int mi = 0; mi < a.m && ok; ++mi) {
                     int64_t acc = 0;
                     for (int j = 0; j < a.n; ++j) {
-                        int64_t sv = (int64_t)u * a.basis[j];
-                        for (int i = 1; i < k; ++i) sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                        sv *= sg;
-                        const int64_t cj2 = 2 * (a.cvec ? a.cvec[j] : 1);
-                        const int64_t tj = sv + rmax;
-                        if (sv > rmax || sv < -rmax || tj % cj2 != 0) {
-                            ok = false;
-                            break;
-                        }
-                        acc += (int64_t)a.A[(size_t)mi * a.n + j] * (tj / cj2);
+                        const int64_t sv = sg * coord(j);
+                        acc += (int64_t)a.A[(size_t)mi * a.n + j] * ((sv + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
                     }
-                    if (ok && acc != a.d[mi]) ok = false;
+                    ok = acc == a.d[mi];
                 }
                 if (ok) {
                     const unsigned long long slot = atomicAdd(a.n_found, 1ull);
                     if ((int64_t)slot < a.cap) {
                         if (a.sol_u) {
                             int8_t *so = a.sol_u + (size_t)slot * k;
-                            so[0] = (int8_t)u;
-                            for (int i = 1; i < k; ++i) so[i] = my_u[k - 1 - i];
+                            for (int i = 0; i < k; ++i) so[i] = my_u[k - 1 - i];
                         }
                         uint8_t *xo = a.x_out + (size_t)slot * a.n;
-                        for (int j = 0; j < a.n; ++j) {
-                            int64_t sv = (int64_t)u * a.basis[j];
-                            for (int i = 1; i < k; ++i)
-                                sv += (int64_t)my_u[k - 1 - i] * a.basis[(size_t)i * a.dim + j];
-                            xo[j] = (uint8_t)((sv * sg + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
-                        }
+                        for (int j = 0; j < a.n; ++j)
+                            xo[j] = (uint8_t)((sg * coord(j) + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
                     }
                     if (a.mode == 1) {
                         atomicCAS(a.t_first, 0ull, wall_clock());
                         atomicOr(&a.flags[0], 1);
                     }
                 }
+                my_u[k - 1] = 0;
                 advance();
             }
             leafpend = 0;
@@ -303,20 +325,20 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 bool cand = state == RUN && top > t && top >= k / 6;
                 int D = top, un = 0, fD = 0, dD = 0;
                 if (cand) {
-                    double yD, lD, bD;
+                    double yD, lD;
                     int uD;
                     if (D == t + 1) {
-                        yD = Py; lD = Pl; bD = Pbt; uD = Pu; fD = Pf; dD = BUDGETED ? Pdsc : 0;
+                        yD = Py; lD = Pl; uD = (int8_t)(Pw & 0xFF); fD = (Pw >> 8) & 0xFF; dD = BUDGETED ? Pdsc : 0;
                     } else {
-                        const double *e = stk + (size_t)D * 4;
+                        const double *e = stack_at(D);
                         yD = e[0]; lD = e[1]; fD = (int)e[2]; dD = BUDGETED ? (int)e[3] : 0;
-                        bD = s_beta[D];
                         uD = my_u[k - 1 - D];
                     }
+                    const double bD = s_beta[D];
                     const int odD = fD & F_ONEDIR, drD = (fD & F_DIRPOS) ? 1 : -1;
                     const Zig zD = zig_init(yD, (fD & F_TZ) != 0);
                     un = odD ? uD + drD : zig_next(zD, uD);
-                    if (BUDGETED && dD + zig_rank(zD, un, (fD & F_TZ) != 0) > budget) {
+                    if (BUDGETED && dD + disc_cost(zD, un, (fD & F_TZ) != 0, dcount) > budget) {
                         // the budget ends level D before its next value
                         top = D - 1;
                         cand = false;
@@ -345,7 +367,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     }
                     base = __shfl(base, leader, 64);
                     valid = __shfl(valid, leader, 64);
-                    const int rank = __popcll(dm & lt_mask);
+                    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(dm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)dm, 0));
                     if (cand && rank < valid) {
                         const int64_t slot = (int64_t)base + rank;
                         int8_t *pu = a.pool.u + slot * k;
@@ -367,7 +389,8 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 if (lane == leader) base = atomicAdd(a.head, (unsigned long long)__popcll(mask));
                 base = __shfl(base, leader, 64);
                 if (need) {
-                    ticket = (long long)(base + __popcll(mask & lt_mask));
+                    ticket = (unsigned)base + (unsigned)__builtin_amdgcn_mbcnt_hi(
+                                                  (unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
                     state = WAIT;
                 }
             }
@@ -376,61 +399,76 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         if (__ballot(state == WAIT)) {
             bool take = false;
             if (state == WAIT) {
-                if (ticket < a.nroots) {
+                if ((long long)ticket < a.nroots) {
                     take = true;
                 } else {
-                    take = ticket < a.pool.cap && ld_acq(&a.pool.ready[ticket]) != 0;
+                    take = (long long)ticket < a.pool.cap && ld_acq(&a.pool.ready[ticket]) != 0;
                     if (!take && ld_rlx(a.pending) == 0) state = DONE;
                 }
             }
+            // Item set-up.  w is only ever changed by code that every lane of
+            // the wave runs (with a zero coefficient where a lane has nothing
+            // to add), never inside a branch that lanes take apart.
+            long long it = 0;
+            int T = 0, mflags = 0, mstart = 0;
+            bool from_root = false;
             if (take) {
-                const long long it = (ticket < a.nroots && a.order) ? a.order[ticket] : ticket;
+                it = ((long long)ticket < a.nroots && a.order) ? a.order[ticket] : (long long)ticket;
                 const int4 mt = a.pool.meta[it];
-                const int T = mt.x;
+                T = mt.x;
+                mstart = mt.y;
+                mflags = mt.z;
+                if (BUDGETED) dsc = mt.w;
                 const int8_t *pu = a.pool.u + it * k;
                 for (int j = 0; j < k; ++j) my_u[k - 1 - j] = j > T ? pu[j] : (int8_t)0;
-                double l = 0.0;
-                if (it < a.nroots) {
-                    // a root from root generation: w and its norm are stored
-                    const double *pw = a.root_w + it * (DIMP + kWsTail) + rot;
+                from_root = it < a.nroots;
+            }
+            // a root from root generation: w and its norm are stored
+            double l = (take && from_root) ? a.root_l[it] : 0.0;
+            if (__ballot(take)) {
+                const double keep = take ? 0.0 : 1.0;
+                const double sel = (take && from_root) ? 1.0 : 0.0;
+                const double *pw = (take && from_root) ? a.root_w + it * (DIMP + kWsTail) + rot : a.g_bh + rot;
 #pragma unroll
-                    for (int q = 0; q < DIMP; q += 2) {
-                        const double2 b = *reinterpret_cast<const double2 *>(pw + q);
-                        w[q] = b.x;
-                        w[q + 1] = b.y;
-                    }
-                    l = a.root_l[it];
-                } else {
-                // prefix: centres, partial norms and w, top level first
-#pragma unroll
-                for (int j = 0; j < DIMP; ++j) w[j] = 0.0;
-                for (int j = k - 1; j > T; --j) {
+                for (int q = 0; q < DIMP; q += 2) {
+                    const double2 b = *reinterpret_cast<const double2 *>(pw + q);
+                    w[q] = fma(sel, b.x, w[q] * keep);
+                    w[q + 1] = fma(sel, b.y, w[q + 1] * keep);
+                }
+            }
+            // a prefix-only item: centres, partial norms and w, top level first
+            const bool pref = take && !from_root;
+            for (int j = k - 1; j >= 1; --j) {
+                const bool act = pref && j > T;
+                if (!__ballot(act)) break;
+                double xj = 0.0;
+                if (act) {
                     const double yj = centre_sum(j, k, my_u, s_muc + s_coff[j]);
-                    const double xj = add_rn((double)my_u[k - 1 - j], yj);
+                    xj = add_rn((double)my_u[k - 1 - j], yj);
                     l = partial_norm(xj, s_beta[j], l);
-                    const double *gr = a.g_bh + (size_t)j * S + rot;
+                }
+                const double *gr = a.g_bh + (size_t)j * S + rot;
 #pragma unroll
-                    for (int q = 0; q < DIMP; q += 2) {
-                        const double2 b = *reinterpret_cast<const double2 *>(gr + q);
-                        w[q] = fma(xj, b.x, w[q]);
-                        w[q + 1] = fma(xj, b.y, w[q + 1]);
-                    }
+                for (int q = 0; q < DIMP; q += 2) {
+                    const double2 b = *reinterpret_cast<const double2 *>(gr + q);
+                    w[q] = fma(xj, b.x, w[q]);
+                    w[q + 1] = fma(xj, b.y, w[q + 1]);
                 }
-                }
+            }
+            if (take) {
                 lpar = l;
                 t = T;
                 top = T;
-                tz = (mt.z & F_TZ) ? 1 : 0;
-                if (BUDGETED) dsc = mt.w;
+                tz = (mflags & F_TZ) ? 1 : 0;
                 bt = s_beta[T];
                 enter_level();
-                if (!(mt.z & F_FRESH)) {
-                    u = mt.y;
-                    onedir = mt.z & F_ONEDIR;
-                    dir = (mt.z & F_DIRPOS) ? 1 : -1;
+                if (!(mflags & F_FRESH)) {
+                    u = mstart;
+                    onedir = mflags & F_ONEDIR;
+                    dir = (mflags & F_DIRPOS) ? 1 : -1;
                 }
                 fex = 0;
-                Pdirty = 0;
+                Pw = 0;
                 state = RUN;
             }
         }
@@ -444,13 +482,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
 #pragma unroll 1
         for (int it = 0; it < kInner; ++it) {
             // ---- control: at most two evaluations and one pop ----
-            int kind = K_NONE, row = 0;
+            int row = 0;
             double coef = 0.0;
-            bool popped = false;
+            bool node = false, popped = false;
             while (state == RUN) {
                 // a discrepancy budget ends the level at the first value whose
-                // rank takes the path beyond it
-                if (BUDGETED && !fex && dsc + zig_rank(z, u, tz != 0) > budget) fex = 1;
+                // cost takes the path beyond it
+                if (BUDGETED && !fex && dsc + disc_cost(z, u, tz != 0, dcount) > budget) fex = 1;
                 if (!fex) {
                     const double x = add_rn((double)u, y);
                     const double l = partial_norm(x, bt, lpar);
@@ -462,7 +500,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                             leafpend = 1;
                             break;
                         }
-                        kind = K_NODE;
+                        node = true;
                         row = t;
                         coef = applied ? (double)(u - u_app) : x;
                         u_app = u;
@@ -485,17 +523,18 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     fex = 1;
                     break;
                 }
-                if (applied) {
-                    kind = K_REVERT;
+                const bool revert = applied != 0;
+                if (revert) {
                     row = t;
                     coef = -add_rn((double)u_app, y);
                 }
                 ++t;
                 y = Py;
                 lpar = Pl;
-                bt = Pbt;
-                u = Pu;
+                bt = s_beta[t];
+                u = (int8_t)(Pw & 0xFF);
                 if (BUDGETED) dsc = Pdsc;
+                const int Pf = (Pw >> 8) & 0xFF;
                 onedir = Pf & F_ONEDIR;
                 dir = (Pf & F_DIRPOS) ? 1 : -1;
                 tz = (Pf & F_TZ) ? 1 : 0;
@@ -503,23 +542,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 u_app = u;
                 applied = 1;
                 if (t + 1 <= top) {
-                    const double *e = stk + (size_t)(t + 1) * 4;
+                    const double *e = stack_at(t + 1);
                     Py = e[0];
                     Pl = e[1];
-                    Pf = (int)e[2];
+                    Pw = (my_u[k - 2 - t] & 0xFF) | (((int)e[2] & 0xFF) << 8);
                     if (BUDGETED) Pdsc = (int)e[3];
-                    Pbt = s_beta[t + 1];
-                    Pu = my_u[k - 2 - t];
-                    Pdirty = 0;
                 }
                 advance();
                 popped = true;
-                if (kind == K_REVERT) break;
+                if (revert) break;
             }
 
-            // ---- the row update, all lanes together ----
-            double h = 0.0;
-            if (__ballot(kind != K_NONE)) {
+            // ---- the row update, all lanes together (a lane without one adds
+            // 0 x row 0, which leaves w as it is) ----
+            double h;
+            {
                 const double *br = s_bh + (size_t)row * S + rot;
                 double h0 = 0.0, h1 = 0.0;
 #pragma unroll
@@ -534,7 +571,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             }
 
             // ---- Hoelder test and the step that follows ----
-            if (kind == K_NODE) {
+            if (node) {
                 const bool fail = hoelder && (lcur > (rmax_d * h) * hfac);
                 if (fail) {
                     if (!onedir_cut) {
@@ -553,23 +590,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         atomicOr(&a.flags[0], 1);
                         state = DONE;
                     } else {
-                        if (Pdirty && t + 1 <= top) {  // only a level first cached here needs writing
-                            double *e = stk + (size_t)(t + 1) * 4;
+                        if ((Pw & 0x10000) && t + 1 <= top) {  // only a level first cached here needs writing
+                            double *e = stack_at(t + 1);
                             e[0] = Py;
                             e[1] = Pl;
-                            e[2] = (double)Pf;
+                            e[2] = (double)((Pw >> 8) & 0xFF);
                             if (BUDGETED) e[3] = (double)Pdsc;
                         }
-                        Pdirty = 1;
                         if (BUDGETED) {
                             Pdsc = dsc;
-                            dsc += zig_rank(z, u, tz != 0);
+                            dsc += disc_cost(z, u, tz != 0, dcount);
                         }
                         Py = y;
                         Pl = lpar;
-                        Pbt = bt;
-                        Pu = u;
-                        Pf = (onedir ? F_ONEDIR : 0) | (dir > 0 ? F_DIRPOS : 0) | (tz ? F_TZ : 0);
+                        Pw = (u & 0xFF) | (((onedir ? F_ONEDIR : 0) | (dir > 0 ? F_DIRPOS : 0) | (tz ? F_TZ : 0)) << 8) |
+                             0x10000;
                         my_u[k - 1 - t] = (int8_t)u;
                         lpar = lcur;
                         tz = (tz && u == 0) ? 1 : 0;
@@ -584,22 +619,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             if (__ballot(state == NEED_ROOT || leafpend != 0) || !__ballot(state == RUN)) break;
         }
     }
-
-    // counters: one atomic per wave
-    for (int o = 32; o >= 1; o >>= 1) {
-        c_eval += __shfl_xor(c_eval, o, 64);
-        c_node += __shfl_xor(c_node, o, 64);
-        c_exp += __shfl_xor(c_exp, o, 64);
-        c_leaf += __shfl_xor(c_leaf, o, 64);
-        c_items += __shfl_xor(c_items, o, 64);
-    }
-    if (lane == 0) {
-        atomicAdd(&a.counters[0], c_eval);
-        atomicAdd(&a.counters[1], c_node);
-        atomicAdd(&a.counters[2], c_exp);
-        atomicAdd(&a.counters[3], c_leaf);
-        atomicAdd(&a.counters[4], c_items);
-    }
+    flush_counters();
 }
 
 hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,

@@ -176,8 +176,18 @@ def test_bad_arguments(M, ctx):
     inst = mi.single_small()
     P = L.prepare(inst.A, inst.d)
     A, d, Bs = _dev(inst.A), _dev(inst.d), _dev(P.basis)
-    r = M.msp_enumerate(ctx, A, d, Bs[:-1].contiguous(), raise_on_error=False)
-    assert r.status == M.MSP_E_ARG
+    # the binding rejects a basis with too few rows before any library call ...
+    with pytest.raises(ValueError):
+        M.msp_enumerate(ctx, A, d, Bs[:-1].contiguous())
+    # ... and the library rejects the same call made straight through the C ABI
+    import ctypes as C
+    m, n = inst.A.shape
+    out = torch.zeros((4, n), dtype=torch.uint8, device=ctx.device)
+    nf, st, prm0 = C.c_int64(0), M.Stats(), M.msp_params_default()
+    rc = M.lib().msp_enumerate(ctx.handle, m, n, A.data_ptr(), d.data_ptr(), Bs.data_ptr(), P.k - 1, M.MSP_ALL,
+                               M.MSP_PLAIN, C.byref(prm0), out.data_ptr(), 4, C.byref(nf), C.byref(st),
+                               torch.cuda.current_stream(ctx.device).cuda_stream)
+    assert rc == M.MSP_E_ARG
     prm = M.msp_params_default(split_depth=P.k)
     r = M.msp_enumerate(ctx, A, d, Bs, params=prm, raise_on_error=False)
     assert r.status == M.MSP_E_ARG
