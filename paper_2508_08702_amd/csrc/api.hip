@@ -358,7 +358,8 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     const double hfac = 1.0 + p.eps;
 
     // ---- root generation: levels k-1 .. L breadth first ----
-    const int64_t walkers = (int64_t)c->num_cus * 256;  // lanes of the walk kernel
+    // lanes of the walk kernel (two waves per SIMD where w is narrow enough)
+    const int64_t walkers = (int64_t)c->num_cus * (dimp <= 88 && p.block != 256 ? 512 : 256);
     const bool ordered_first = mode == MSP_FIRST && order != MSP_PLAIN;
     const bool refine = ordered_first && p.refine != 0;
     const int max_stages = p.refine > 0 ? p.refine : 64;

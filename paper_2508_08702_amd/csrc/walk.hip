@@ -43,7 +43,7 @@ namespace msp {
 
 namespace {
 
-enum : int { NEED_ROOT = 0, RUN = 1, DONE = 2, WAIT = 3 };
+enum : int { NEED_ROOT = 0, RUN = 1, DONE = 2, WAIT = 3, LOAD = 4 };
 enum : int { K_NONE = 0, K_NODE = 1, K_REVERT = 2 };
 enum : int { F_ONEDIR = 1, F_DIRPOS = 2, F_TZ = 4, F_FRESH = 8 };
 
@@ -160,12 +160,20 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
 // level and its parent, 32-bit counters), so that at DIMP <= 88 two waves
 // fit on a SIMD.  The parent level's state is cached in registers and the
 // grandparent is read back from the per-walker stack on a pop.
+//
+// ALLROWS (the two-wave variant): every row b_hat_0..b_hat_{k-1} is in LDS,
+// and a lane that takes an item rebuilds the prefix's w with ordinary row
+// updates of the inner loop, one prefix level per iteration (state LOAD),
+// which keeps the rare-work pass small.  Otherwise only rows below the split
+// level are in LDS, and the prefix is rebuilt in the rare-work pass from the
+// rows in HBM (or loaded, for a root that root generation stored).
 template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
-    constexpr int kInner = 32;  // iterations of the inner loop between rare-work passes
+    constexpr int kInner = 128;  // most iterations of the inner loop between rare-work passes
+    constexpr bool ALLROWS = BLOCK == 512;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int k = a.k, L = a.L, tid = threadIdx.x;
+    const int k = a.k, L = ALLROWS ? a.k : a.L, tid = threadIdx.x;
     const int KU = walk_u_stride(k);
     double *s_bh = reinterpret_cast<double *>(smem);  // L x S
     double *s_muc = s_bh + (size_t)L * S;             // mu columns
@@ -409,6 +417,25 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             // Item set-up.  w is only ever changed by code that every lane of
             // the wave runs (with a zero coefficient where a lane has nothing
             // to add), never inside a branch that lanes take apart.
+            if (ALLROWS) {
+                if (take) {
+                    const long long it = ((long long)ticket < a.nroots && a.order) ? a.order[ticket] : (long long)ticket;
+                    const int4 mt = a.pool.meta[it];
+                    if (BUDGETED) dsc = mt.w;
+                    const int8_t *pu = a.pool.u + it * k;
+                    for (int j = 0; j < k; ++j) my_u[k - 1 - j] = j > mt.x ? pu[j] : (int8_t)0;
+                    top = mt.x;
+                    t = k - 1;          // next prefix level to add
+                    lpar = 0.0;         // partial norm of the prefix so far
+                    Pw = (mt.y & 0xFF) | ((mt.z & 0xFF) << 8);  // continuation, kept until the level is entered
+                    state = LOAD;
+                }
+                if (__ballot(take)) {
+                    const double keep = take ? 0.0 : 1.0;
+#pragma unroll
+                    for (int q = 0; q < DIMP; ++q) w[q] *= keep;
+                }
+            } else {
             long long it = 0;
             int T = 0, mflags = 0, mstart = 0;
             bool from_root = false;
@@ -471,9 +498,10 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 Pw = 0;
                 state = RUN;
             }
+            }
         }
         if (__ballot(state != DONE) == 0) break;
-        if (__ballot(state == RUN) == 0) {
+        if (__ballot(state == RUN || state == LOAD) == 0) {
             __builtin_amdgcn_s_sleep(32);  // the whole wave is waiting: back off
             continue;
         }
@@ -485,6 +513,31 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             int row = 0;
             double coef = 0.0;
             bool node = false, popped = false;
+            if (ALLROWS && state == LOAD) {
+                // one prefix level per iteration, top level first
+                if (t > top) {
+                    const double yj = centre_sum(t, k, my_u, s_muc + s_coff[t]);
+                    const double xj = add_rn((double)my_u[k - 1 - t], yj);
+                    lpar = partial_norm(xj, s_beta[t], lpar);
+                    row = t;
+                    coef = xj;
+                    --t;
+                }
+                if (t == top) {  // the prefix is complete: enter the item's level
+                    const int mstart = (int8_t)(Pw & 0xFF), mflags = (Pw >> 8) & 0xFF;
+                    tz = (mflags & F_TZ) ? 1 : 0;
+                    bt = s_beta[t];
+                    enter_level();
+                    if (!(mflags & F_FRESH)) {
+                        u = mstart;
+                        onedir = mflags & F_ONEDIR;
+                        dir = (mflags & F_DIRPOS) ? 1 : -1;
+                    }
+                    fex = 0;
+                    Pw = 0;
+                    state = RUN;
+                }
+            } else
             while (state == RUN) {
                 // a discrepancy budget ends the level at the first value whose
                 // cost takes the path beyond it
@@ -614,9 +667,12 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     }
                 }
             }
-            // leave for the rare-work pass when some lane needs it (waiting lanes
+            // leave for the rare-work pass when a leaf waits for its check, when
+            // eight lanes wait for work, or when no lane has any (waiting lanes
             // are served there too, but only every kInner iterations)
-            if (__ballot(state == NEED_ROOT || leafpend != 0) || !__ballot(state == RUN)) break;
+            if (__ballot(leafpend != 0) || __popcll(__ballot(state == NEED_ROOT)) >= 8 ||
+                !__ballot(state == RUN || state == LOAD))
+                break;
         }
     }
     flush_counters();
@@ -641,7 +697,8 @@ static hipError_t launch_variant(const WalkArgs &a, int num_cus, size_t lds, hip
 
 template <int DIMP, int BLOCK>
 static hipError_t launch_one(const WalkArgs &a, int num_cus, hipStream_t st) {
-    const size_t lds = walk_lds_bytes(DIMP, BLOCK, a.k, a.L, a.muc_len);
+    // the two-wave variant keeps every row in LDS
+    const size_t lds = walk_lds_bytes(DIMP, BLOCK, a.k, BLOCK == 512 ? a.k : a.L, a.muc_len);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     return a.budget >= 0 ? launch_variant<DIMP, BLOCK, true>(a, num_cus, lds, st)
                          : launch_variant<DIMP, BLOCK, false>(a, num_cus, lds, st);
@@ -654,6 +711,8 @@ int walk_max_level(int dimp, int k) {
 }
 
 int walk_block_for(int dimp, int k, int L) {
+    // two waves per SIMD where w is small enough, else one
+    if (dimp <= 88 && walk_lds_bytes(dimp, 512, k, k, walk_muc_len(k)) <= 160 * 1024) return 512;
     return walk_lds_bytes(dimp, 256, k, L, walk_muc_len(k)) <= 160 * 1024 ? 256 : 0;
 }
 
