@@ -168,6 +168,20 @@ void msp_ctx_destroy(msp_ctx *ctx);
 int msp_reduce(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
                const msp_params *p, int64_t *basis_dev, int *k_out, void *stream);
 
+/* msp_reduce without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It needs no context: it works on the calling thread's current
+ * device, and `stream` must belong to that device.  Arguments, layouts and
+ * results are those of msp_reduce with LLL only (p->bkz_block must be 0, or
+ * MSP_E_ARG); k is returned in *k_out after the stream is synchronised.
+ * Scratch: a file-scope device array of 261,376 bytes per GPU (a launch
+ * descriptor and the (n+1) x (m+n+1) int64 embedding workspace, enough for
+ * every n <= MSP_MAX_N), held until the process ends; a size beyond it is
+ * rejected with MSP_E_ARG.  Calls that overlap on one GPU share the array and
+ * race; serialise them. */
+int msp_reduce_noalloc(int m, int n, const int32_t *A_dev, const int64_t *d_dev, const msp_params *p,
+                       int64_t *basis_dev, int *k_out, void *stream);
+
 /* Step 3 of Algorithm 1 (eq. (4)): FP64 Gram-Schmidt of a kernel basis.
  * basis_dev: int64 k x dim.  Outputs (device, caller-allocated):
  * bhat_dev k x dim (row i = b_hat_i), mu_dev k x k (mu_dev[i*k+j] = mu_ij for

@@ -44,7 +44,7 @@ EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_solve_first", "msp_strerror",
     "msp_reduce_bounded", "msp_enumerate_bounded", "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
-    "msp_model_grad", "msp_train_params_default", "msp_model_train",
+    "msp_model_grad", "msp_train_params_default", "msp_model_train", "msp_reduce_noalloc",
 )
 
 
@@ -142,6 +142,8 @@ def _load() -> C.CDLL:
     lib.msp_train_params_default.restype = i32
     lib.msp_model_train.argtypes = [vp, vp, vp, i64, C.POINTER(TrainParams), vp, vp]
     lib.msp_model_train.restype = i32
+    lib.msp_reduce_noalloc.argtypes = [i32, i32, vp, vp, C.POINTER(Params), vp, C.POINTER(i32), vp]
+    lib.msp_reduce_noalloc.restype = i32
     lib.msp_strerror.argtypes = [i32]
     lib.msp_strerror.restype = C.c_char_p
     return lib
@@ -318,6 +320,32 @@ def msp_reduce(ctx: Context, A: torch.Tensor, d: torch.Tensor, params: Params | 
     if rc != MSP_OK:
         raise MspError(rc, "msp_reduce")
     return basis[: k.value].contiguous()
+
+
+def msp_reduce_noalloc(A: torch.Tensor, d: torch.Tensor, params: Params | None = None,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+    """msp_reduce without a context and without any device allocation in the
+    library (its scratch is a fixed device array).  Runs on A's device; the
+    int64 kernel basis is written to ``out`` ((n+1) x (n+1) rows available,
+    allocated here when not given) and returned as its first k rows."""
+    m, n = _check_instance(A, d)
+    dev = A.device
+    if dev.type != "cuda":
+        raise ValueError("msp_reduce_noalloc needs device tensors")
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    if out is None:
+        out = torch.zeros((n + 1, n + 1), dtype=torch.int64, device=dev)
+    elif _check_out(out, n + 1, "out") < n + 1:
+        raise ValueError(f"out must have n + 1 = {n + 1} rows")
+    _dev_ptr(out, torch.int64, dev, "out")
+    k = C.c_int(0)
+    p = params if params is not None else msp_params_default()
+    with torch.cuda.device(dev):
+        rc = lib().msp_reduce_noalloc(m, n, ap, dp, C.byref(p), out.data_ptr(), C.byref(k), _stream_handle(dev))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_reduce_noalloc")
+    return out[: k.value]
 
 
 @dataclass

@@ -729,14 +729,6 @@ int msp_enumerate(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t 
 }
 
 namespace {
-// per-instance descriptor of a reduction launch
-struct LllDesc {
-    int m, n;
-    int64_t A_off, d_off, work_off, out_off;
-    int32_t status, kout;
-    long long iters;
-};
-
 int lll_status(int32_t st) {
     switch (st) {
         case 0: return MSP_OK;

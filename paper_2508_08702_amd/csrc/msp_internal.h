@@ -239,6 +239,14 @@ struct LllArgs {
     int stride;                    // distance between instances, in 4-byte units
 };
 hipError_t launch_lll(const LllArgs &a, int ninst, int max_n, hipStream_t st);
+// per-instance descriptor of a reduction launch (the kernel reads its fields
+// through the strided views of LllArgs)
+struct LllDesc {
+    int m, n;
+    int64_t A_off, d_off, work_off, out_off;
+    int32_t status, kout;
+    long long iters;
+};
 // r_max = lcm(r_0..r_{n-1}) and c_j = r_max / r_j; *rmax = -1 when some
 // r_j is outside 1..255, -2 when r_max would exceed 2^20
 hipError_t launch_bounds_scale(const int32_t *r, int n, int64_t *cvec, long long *rmax, hipStream_t st);
