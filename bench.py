@@ -1,11 +1,12 @@
 """Benchmark: lattice enumeration for market split instances on one MI355X.
 
 One step = the whole GPU path for every instance of the workload: embedding +
-LLL + kernel extraction (msp_reduce), Gram-Schmidt, root generation and the
-exhaustive subtree walk (msp_enumerate, mode all).  Inputs (A, d) are resident
-on the device before timing starts.  The headline value is enumeration nodes
-per second over the whole step (a node is a candidate that passed the l2
-test), i.e. total nodes / wall time of the step.
+LLL (+ BKZ with --bkz) + kernel extraction (msp_reduce),
+Gram-Schmidt, root generation and the exhaustive subtree walk (msp_enumerate,
+mode all).  Inputs (A, d) are resident on the device before timing starts.
+The headline value is enumeration nodes per second over the whole step (a
+node is a candidate that passed the l2 test), i.e. total nodes / wall time
+of the step.
 
 Also reported:
   roofline      the walk kernel against FP64 vector peak: algorithmic flops
@@ -13,13 +14,17 @@ Also reported:
                 coordinates plus the partial-norm recurrence) and 4 per
                 candidate that fails the l2 test, divided by the walk kernel's
                 measured duration (HIP events on its launch stream);
-  ttfs          time to the first verified solution (mode first) per
-                instance of a TTFS set (12 planted instances, m=9 or m=11),
-                plain depth-first root order against the learned root order
-                (the committed root-scoring model), same split and kernel;
-                each run is capped (a capped run is reported as "> cap");
-  cpu_baseline  the CPU oracle (plain recursive C enumerator, all host cores)
-                on a time-capped sample of the first instance.
+  ttfs          time to the first verified solution per instance of the
+                TTFS sets (12 planted instances each): m=9 on LLL bases,
+                depth-first search in plain root order against the learned
+                root order (the committed root-scoring model); m=11 on BKZ-16
+                bases, limited discrepancy search in plain against learned
+                root order.  Each instance is reduced once; both orders then
+                search the same basis.  Each search is capped (a capped run
+                is censored and counts as the cap in the medians);
+  cpu_baseline  the CPU oracle (plain recursive C enumerator, all host cores,
+                the host CPU model named) on a time-capped sample of the
+                first instance.
 """
 from __future__ import annotations
 
@@ -37,13 +42,10 @@ if ROOT not in sys.path:
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 
 # HBM bytes per walk-kernel launch measured with rocprofv3 counters
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scale factors from a 1 GiB copy in the
-# same run), valid only for the kernel source they were taken on.
-WALK_TRAFFIC = {
-    "m9-1": {"bytes": 3.479e12,
-             "sha256": "cd385812b38cb41c994ee864603c1f16086a4518b4466870704f1df5dc8ad74d",
-             "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
-}
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for a
+# 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
+# valid only for the kernel source they were taken on.
+WALK_TRAFFIC = {}
 
 
 def walk_source_hash() -> str:
@@ -70,26 +72,35 @@ WORKLOADS = {
 }
 
 
+# first-solution sets: reduction and the two strategies compared on it
+TTFS_SETS = {
+    "m9": {"bkz": 0, "orders": "plain,learned", "cap_ms": 6000.0},
+    "m11": {"bkz": 16, "orders": "lds,lds-learned", "cap_ms": 8000.0},
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="m9-1", choices=sorted(WORKLOADS))
-    ap.add_argument("--ttfs", default="m9", choices=("none", "m9", "m11"),
-                    help="first-solution set timed per order (none to skip)")
-    ap.add_argument("--ttfs-cap-ms", type=float, default=10000.0)
-    ap.add_argument("--ttfs-seeds", default="", help="comma-separated subset of the TTFS set's seeds")
-    ap.add_argument("--orders", default="plain,learned", help="orders timed on the TTFS set")
+    ap.add_argument("--ttfs", default="m9,m11",
+                    help="comma-separated first-solution sets timed per order (m9, m11; none to skip)")
+    ap.add_argument("--ttfs-cap-ms", type=float, default=0.0, help="cap per search (0: the set's default)")
+    ap.add_argument("--ttfs-seeds", default="", help="comma-separated subset of the TTFS sets' seeds")
+    ap.add_argument("--orders", default="", help="orders timed on every TTFS set (empty: the set's default)")
+    ap.add_argument("--ttfs-bkz", type=int, default=-1, help="BKZ block size of the TTFS reductions (-1: the set's)")
     ap.add_argument("--batch", action="store_true",
                     help="also time the uneven 96-instance batch (msp_solve_batch) with autotuned root counts")
-    ap.add_argument("--bkz", type=int, default=0, help="BKZ block size for every reduction (0: LLL only)")
+    ap.add_argument("--bkz", type=int, default=0,
+                    help="BKZ block size of the main workload's reduction (0: LLL only)")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2508_08702_amd", "order_model.npy"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this size (a known-size kernel that "
                          "calibrates HBM byte counters in a profile of this command)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--time-cap-ms", type=float, default=600000.0)
     return ap.parse_args()
 
@@ -128,10 +139,14 @@ def batch_run(M, ctx, args, np, torch, mi, dev):
             "tune_points": [{"target_roots": t, "status": s_, "ms": ms} for t, s_, ms in pts]}
 
 
-def ttfs_set(M, ctx, args, np, torch, mi, dev):
-    """First-solution search per instance and order; end-to-end times
-    include msp_reduce, root generation, root ordering and the walk."""
-    insts = mi.m9_eval() if args.ttfs == "m9" else mi.m11_eval()
+def ttfs_set(M, ctx, args, np, torch, mi, dev, which):
+    """First-solution search per instance and order.  Each instance is
+    reduced once (timed); every order then searches that basis, so the
+    end-to-end time of an order is the reduction plus its own search."""
+    cfg = TTFS_SETS[which]
+    bkz = cfg["bkz"] if args.ttfs_bkz < 0 else args.ttfs_bkz
+    cap = args.ttfs_cap_ms if args.ttfs_cap_ms > 0 else cfg["cap_ms"]
+    insts = mi.m9_eval() if which == "m9" else mi.m11_eval()
     if args.ttfs_seeds:
         keep = {int(x) for x in args.ttfs_seeds.split(",")}
         insts = [i for i in insts if i.seed in keep]
@@ -140,59 +155,91 @@ def ttfs_set(M, ctx, args, np, torch, mi, dev):
     orders = {"plain": (M.MSP_FIRST, M.MSP_PLAIN), "learned": (M.MSP_FIRST, M.MSP_LEARNED),
               "discrepancy": (M.MSP_FIRST, M.MSP_DISCREPANCY), "lds": (M.MSP_LDS, M.MSP_PLAIN),
               "lds-learned": (M.MSP_LDS, M.MSP_LEARNED)}
-    names = [o for o in args.orders.split(",") if o]
+    names = [o for o in (args.orders or cfg["orders"]).split(",") if o]
     if any(o.endswith("learned") for o in names):
         M.msp_model_set(ctx, np.load(args.model))
     per = []
     for inst in insts:
+        if not per:
+            print(f"  ttfs {which}: {len(insts)} instances, orders {names}, cap {cap:.0f} ms", file=sys.stderr,
+                  flush=True)
         A = torch.from_numpy(inst.A).to(dev)
         d = torch.from_numpy(inst.d).to(dev)
         row = {"m": inst.m, "D": int(inst.D), "seed": int(inst.seed)}
+        red_ms = None
+        Bk = None
         for name in names:
-            prm = M.msp_params_default(time_cap_ms=args.ttfs_cap_ms, bkz_block=args.bkz)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            prm = M.msp_params_default(time_cap_ms=cap, bkz_block=bkz)
             if name.startswith("lds-r"):
                 # "lds-r<R>[-learned]": LDS over R shuffled copies, reduced together
                 prm.restarts = int(name[5:].split("-")[0])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 r = M.msp_solve_first(ctx, A, d, params=prm, cap=64, raise_on_error=False,
                                       order=M.MSP_LEARNED if name.endswith("-learned") else M.MSP_PLAIN)
+                torch.cuda.synchronize()
+                e2e = (time.perf_counter() - t0) * 1e3
             else:
-                Bk = M.msp_reduce(ctx, A, d, prm)
+                if Bk is None:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    Bk = M.msp_reduce(ctx, A, d, prm)
+                    torch.cuda.synchronize()
+                    red_ms = (time.perf_counter() - t0) * 1e3
                 mode, order = orders[name]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 r = M.msp_enumerate(ctx, A, d, Bk, params=prm, mode=mode, order=order, cap=64,
                                     raise_on_error=False)
-            torch.cuda.synchronize()
-            e2e = (time.perf_counter() - t0) * 1e3
+                torch.cuda.synchronize()
+                e2e = red_ms + (time.perf_counter() - t0) * 1e3
             xs = r.x.cpu().numpy().astype(np.int64)
             ok = xs.shape[0] > 0 and bool(np.all(xs @ inst.A.T.astype(np.int64) == inst.d[None, :]))
             if r.n_found and not ok:
                 raise RuntimeError("a first-mode row does not satisfy A x = d")
             st = r.stats
             row[name] = {"ttfs_ms": st["ttfs_ms"] if ok else None, "end_to_end_ms": e2e if ok else None,
-                         "censored": not ok, "status": r.status, "roots": st["roots"],
+                         "censored": not ok, "status": r.status, "nodes": st["nodes"], "evals": st["evals"],
+                         "search_ms": st["total_ms"], "roots": st["roots"],
                          "split_depth": st["split_depth"], "ordering_ms": st["ordering_ms"],
                          "rootgen_ms": st["rootgen_ms"], "stages": st["stages"], "root_level": st["root_level"],
                          "initial_items": st["initial_items"]}
             if name.startswith("lds-r"):
                 row[name]["copy"] = st["copy"]
+        if red_ms is not None:
+            row["reduce_ms"] = red_ms
         print(json.dumps({"ttfs_instance": row}), file=sys.stderr, flush=True)
         per.append(row)
 
     def med(name):
         # a censored run counts as the cap (a lower bound on its true time)
-        v = [r[name]["end_to_end_ms"] if not r[name]["censored"] else args.ttfs_cap_ms for r in per]
+        v = [r[name]["end_to_end_ms"] if not r[name]["censored"] else cap for r in per]
         return statistics.median(v)
 
     out = {"set": f"{len(insts)} planted instances m={insts[0].m}, n={insts[0].n}, 4 each D=50/100/200",
-           "reduction": f"BKZ-{args.bkz}" if args.bkz else "LLL",
-           "mode": "first", "cap_ms": args.ttfs_cap_ms,
+           "reduction": f"BKZ-{bkz}" if bkz else "LLL",
+           "mode": "first", "cap_ms": cap, "orders": names,
            "median_end_to_end_ms": {n: med(n) for n in names},
            "censored": {n: sum(r[n]["censored"] for r in per) for n in names},
+           "solved_within_cap": {n: sum(not r[n]["censored"] for r in per) for n in names},
            "per_instance": per}
-    if "plain" in names and "learned" in names:
-        out["median_plain_over_learned"] = med("plain") / med("learned")
+    if len(names) == 2:
+        a_, b_ = names
+        out[f"median_{a_}_over_{b_}"] = med(a_) / med(b_)
     return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def main():
@@ -265,7 +312,7 @@ def main():
         flops += st["nodes"] * (3 * dim + 4) + (st["evals"] - st["nodes"]) * 4
         kern_s += st["kernel_ms"] * 1e-3
     achieved = flops / kern_s / 1e12 if kern_s > 0 else 0.0
-    tr = WALK_TRAFFIC.get(args.workload)
+    tr = WALK_TRAFFIC.get((args.workload, args.bkz))
     traffic = tr["bytes"] if tr and tr["sha256"] == walk_source_hash() else None
     res = {
         "metric": "enum nodes/s + time-to-first-solution, m=9..11, plain vs learned order",
@@ -294,8 +341,12 @@ def main():
             for k in ("gs_ms", "rootgen_ms", "kernel_ms", "total_ms")
         },
     }
-    if args.ttfs != "none":
-        res["ttfs"] = ttfs_set(M, ctx, args, np, torch, mi, dev)
+    sets = [x for x in args.ttfs.split(",") if x and x != "none"]
+    for which in sets:
+        if which not in TTFS_SETS:
+            raise SystemExit(f"unknown TTFS set {which}")
+    if sets:
+        res["ttfs"] = {which: ttfs_set(M, ctx, args, np, torch, mi, dev, which) for which in sets}
     if args.batch:
         res["batch"] = batch_run(M, ctx, args, np, torch, mi, dev)
     if not args.no_cpu_baseline:
@@ -306,6 +357,7 @@ def main():
         cores = os.cpu_count() or 1
         r = E.enumerate_prepared(P, split=12, threads=cores, time_cap_s=args.cpu_seconds)
         res["cpu_baseline"] = {"value": r.nodes / r.seconds, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+                               "cpu_model": cpu_model(),
                                "sample": f"instance m={inst.m} D={inst.D} seed={inst.seed}, first "
                                          f"{r.seconds:.1f} s of the exhaustive enumeration (time cap), "
                                          f"{r.nodes} nodes"}

@@ -22,8 +22,8 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_figure_matches_its_profile():
     import bench
-    for workload, tr in bench.WALK_TRAFFIC.items():
-        assert workload in bench.WORKLOADS
+    for (workload, bkz), tr in bench.WALK_TRAFFIC.items():
+        assert workload in bench.WORKLOADS and bkz >= 0
         path = os.path.join(ROOT, tr["profile"])
         txt = open(path).read()
         assert tr["sha256"] in txt
