@@ -115,6 +115,9 @@ typedef struct {
     int restarts;         /* msp_solve_first: shuffled copies of the instance,
                            * 1..64 (copy 0 keeps the given variable order)       [1] */
     uint32_t restart_seed;/* msp_solve_first: seed of the shuffles               [1] */
+    int disc_count;       /* reading of a discrepancy (Section 3): 0 = a value's
+                           * rank in its level's value order, 1 = one for every
+                           * value other than the level's first              [0] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).

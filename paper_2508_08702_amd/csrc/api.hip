@@ -199,6 +199,7 @@ int msp_params_default(msp_params *p) {
     p->bkz_tours = 4;
     p->restarts = 1;
     p->restart_seed = 1;
+    p->disc_count = 0;
     return MSP_OK;
 }
 
@@ -328,6 +329,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     if (pin) p = *pin;
     if (!(p.eps >= 0.0) || p.split_depth < -1 || p.split_depth > k - 1) return MSP_E_ARG;
     if (p.refine < -1 || p.refine_keep < 0 || p.target_roots < 0 || p.disc_budget > 255) return MSP_E_ARG;
+    if (p.disc_count != 0 && p.disc_count != 1) return MSP_E_ARG;
     *n_found = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -409,6 +411,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             ea.hfac = hfac;
             ea.rmax = (double)rmax;
             ea.budget = p.disc_budget;
+            ea.disc_count = p.disc_count;
             ea.hoelder = p.hoelder;
             ea.onedir = p.onedir;
             ea.counters = ctl->counters;
@@ -603,6 +606,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.rmax = rmax;
         wa.cvec = cvec;
         wa.budget = p.disc_budget;
+        wa.disc_count = p.disc_count;
         wa.hoelder = p.hoelder;
         wa.onedir = p.onedir;
         MSP_TRY(hipEventRecord(c->ev[4], st));

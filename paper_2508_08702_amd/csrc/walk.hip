@@ -48,6 +48,17 @@ enum : int { K_NONE = 0, K_NODE = 1, K_REVERT = 2 };
 enum : int { F_ONEDIR = 1, F_DIRPOS = 2, F_TZ = 4, F_FRESH = 8 };
 
 constexpr int kRot = 2;  // rotation granule (columns): 128-bit reads
+#ifndef MSP_WALK_INNER
+#define MSP_WALK_INNER 1024
+#endif
+#ifndef MSP_WALK_ROTS
+#define MSP_WALK_ROTS 8
+#endif
+#ifndef MSP_WALK_ROWALIGN
+#define MSP_WALK_ROWALIGN 16
+#endif
+constexpr int kRowWrap = 2 * (MSP_WALK_ROTS - 1);  // wrap-around columns of a row: the largest rotation
+constexpr int kRowAlign = MSP_WALK_ROWALIGN;        // row stride granule (doubles)
 
 __device__ __forceinline__ unsigned long long wall_clock() { return wall_clock64(); }
 
@@ -102,7 +113,7 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
 
 }  // namespace
 
-__host__ __device__ int walk_row_stride(int dimp) { return ((dimp + kRotMax + 15) / 16) * 16; }
+__host__ __device__ int walk_row_stride(int dimp) { return ((dimp + kRowWrap + kRowAlign - 1) / kRowAlign) * kRowAlign; }
 // per-thread u row: an odd number of 8-byte words, so 16 lanes reading the
 // same word index hit 16 distinct bank pairs
 __host__ __device__ int walk_u_stride(int k) {
@@ -134,7 +145,7 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
     if (t < k) {
         for (int p = threadIdx.x; p < S; p += blockDim.x) {
             double v = 0.0;
-            if (p < dimp + kRotMax) {
+            if (p < dimp + kRowWrap) {
                 const int c = p < dimp ? p : p - dimp;
                 if (c < dim) v = bhat[(size_t)t * dim + c];
             }
@@ -169,11 +180,13 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
 // rows in HBM (or loaded, for a root that root generation stored).
 template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
-    constexpr int S = ((DIMP + kRotMax + 15) / 16) * 16;
-    constexpr int kInner = 128;  // most iterations of the inner loop between rare-work passes
+    constexpr int S = ((DIMP + kRowWrap + kRowAlign - 1) / kRowAlign) * kRowAlign;
+    constexpr int kInner = MSP_WALK_INNER;  // most iterations of the inner loop between rare-work passes
     constexpr bool ALLROWS = BLOCK == 512;
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k, L = ALLROWS ? a.k : a.L, tid = threadIdx.x;
+    double *const stack_base = a.stack;
+    int *const flagsp = a.flags;
     const int KU = walk_u_stride(k);
     double *s_bh = reinterpret_cast<double *>(smem);  // L x S
     double *s_muc = s_bh + (size_t)L * S;             // mu columns
@@ -189,7 +202,9 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     __syncthreads();
 
     const int lane = tid & 63;
-    const int rot = kRot * (lane & 7);
+    // rotation of the lane's columns: 8 or 16 distinct rotations with every row
+    // in LDS; 8 otherwise (a stored root's w is padded for 8 only)
+    const int rot = kRot * (lane & (ALLROWS ? MSP_WALK_ROTS - 1 : 7));
     int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
     const double bound = a.bound, hfac = a.hfac, rmax_d = a.rmax_d;
     const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
@@ -197,7 +212,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     const bool dcount = a.disc_count != 0;
     // this walker's stack: k entries of {centre, partial norm of the parent, flags, discrepancies}
     auto stack_at = [&](int level) -> double * {
-        return a.stack + ((size_t)(blockIdx.x * BLOCK + tid) * (size_t)k + (size_t)level) * 4;
+        return stack_base + ((size_t)(blockIdx.x * BLOCK + tid) * (size_t)k + (size_t)level) * 4;
     };
 
     double w[DIMP];
@@ -639,8 +654,8 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 } else {
                     ++c_exp;
                     if (u > 127 || u < -127) {
-                        atomicOr(&a.flags[1], 1);
-                        atomicOr(&a.flags[0], 1);
+                        atomicOr(&flagsp[1], 1);
+                        atomicOr(&flagsp[0], 1);
                         state = DONE;
                     } else {
                         if ((Pw & 0x10000) && t + 1 <= top) {  // only a level first cached here needs writing
@@ -717,10 +732,10 @@ int walk_block_for(int dimp, int k, int L) {
 }
 
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st) {
-#define MSP_CASE(D)                                                           \
-    case D:                                                                   \
+#define MSP_CASE(D)                                                             \
+    case D:                                                                     \
         if (block == 512 && D <= 88) return launch_one<D, 512>(a, num_cus, st); \
-        if (block == 256) return launch_one<D, 256>(a, num_cus, st);          \
+        if (block == 256) return launch_one<D, 256>(a, num_cus, st);            \
         return hipErrorInvalidValue;
     switch (dimp) {
         MSP_CASE(24) MSP_CASE(32) MSP_CASE(40) MSP_CASE(48) MSP_CASE(52) MSP_CASE(56) MSP_CASE(64)

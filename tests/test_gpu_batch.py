@@ -3,7 +3,10 @@ instances: m drawn from 5..8 per instance, n = 10(m-1), D by thirds.
 
 The batch reduces every instance in one LLL launch and then enumerates each
 one, so its bases, solution sets and search-tree counters must equal those
-of the single-instance calls; solution sets must equal the oracle's.
+of the single-instance calls; solution sets must equal the oracle's: for
+m <= 6 the oracle runs here, for m = 7 and 8 its sets are stored
+(tests/golden/batch_sets.json, written by tests/golden/make_batch_sets.py from
+oracle/ alone).
 """
 from __future__ import annotations
 
@@ -83,6 +86,23 @@ def test_batch_oracle_parity_small_m(M, ctx, batch):
         x = E.sort_rows(r.x[i].cpu().numpy())
         assert r.n_found[i] == ref.n_found, f"seed {inst.seed}"
         assert np.array_equal(x, ref.solutions), f"seed {inst.seed}"
+
+
+def test_batch_oracle_parity_large_m(M, ctx, batch):
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_sets.json")
+    stored = json.load(open(path))["instances"]
+    large = [inst for inst in batch if inst.m >= 7]
+    assert len(large) == len(stored) and {str(i.seed) for i in large} == set(stored)
+    r = _run_batch(M, ctx, large)
+    assert r.rc == M.MSP_OK
+    for i, inst in enumerate(large):
+        g = stored[str(inst.seed)]
+        assert (g["m"], g["n"], g["D"]) == (inst.m, inst.n, int(inst.D))
+        x = E.sort_rows(r.x[i].cpu().numpy())
+        assert r.n_found[i] == g["n_found"], f"seed {inst.seed}"
+        assert np.array_equal(x, E.sort_rows(np.array(g["solutions"], dtype=np.uint8).reshape(-1, inst.n))), \
+            f"seed {inst.seed}"
 
 
 def _small(batch, count):

@@ -1,6 +1,9 @@
 """GPU limited discrepancy search (paper, Section 3) against the oracle: the
-budgeted exhaustive walk (same nodes, same solutions for each budget) and the
-first-solution mode that raises the budget pass by pass."""
+budgeted exhaustive walk (same nodes, same solutions for each budget) under
+both readings of a discrepancy (rank in the level's value order, or one per
+departure from the level's first value), at m = 6..7 and at m = 11 (n = 100,
+the wide walker variant), and the first-solution mode that raises the budget
+pass by pass."""
 from __future__ import annotations
 
 import os
@@ -33,14 +36,29 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
 
 
-@pytest.mark.parametrize("m,D,seed", [(6, 100, 2000), (6, 50, 2003), (7, 100, 4100)])
-@pytest.mark.parametrize("B", [0, 1, 2, 5])
-def test_budgeted_walk_matches_oracle(M, ctx, m, D, seed, B):
+_PREP = {}
+
+
+def _prepared(m, D, seed):
+    """The oracle's exact reduction of one planted instance, computed once."""
+    key = (m, D, seed)
+    if key not in _PREP:
+        inst = mi.msp_class(m, D, seed)
+        _PREP[key] = L.prepare(inst.A, inst.d)
+    return _PREP[key]
+
+
+@pytest.mark.parametrize("count", [0, 1])
+@pytest.mark.parametrize("m,D,seed", [(6, 100, 2000), (6, 50, 2003), (7, 100, 4100),
+                                      (11, 50, 5000), (11, 100, 5004), (11, 200, 5008)])
+@pytest.mark.parametrize("B", [0, 1, 2, 4])
+def test_budgeted_walk_matches_oracle(M, ctx, m, D, seed, B, count):
     inst = mi.msp_class(m, D, seed)
-    P = L.prepare(inst.A, inst.d)
-    ref = E.enumerate_prepared(P, split=6, threads=os.cpu_count() or 1, disc_budget=B)
-    print(f"  budget {B} m={m} D={D} seed={seed}: oracle {ref.nodes} nodes", flush=True)
-    prm = M.msp_params_default(time_cap_ms=60000.0, disc_budget=B)
+    P = _prepared(m, D, seed)
+    ref = E.enumerate_prepared(P, split=6, threads=os.cpu_count() or 1, disc_budget=B, disc_count=bool(count))
+    print(f"  budget {B} ({'count' if count else 'rank'}) m={m} D={D} seed={seed}: oracle {ref.nodes} nodes",
+          flush=True)
+    prm = M.msp_params_default(time_cap_ms=60000.0, disc_budget=B, disc_count=count)
     r = M.msp_enumerate(ctx, _dev(inst.A), _dev(inst.d), _dev(P.basis), params=prm)
     assert r.status == M.MSP_OK and r.n_found == ref.n_found
     assert np.array_equal(E.sort_rows(r.x.cpu().numpy()), ref.solutions)
