@@ -535,11 +535,11 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     if (p.block != 0 && wblock != 0) wblock = std::min(wblock, p.block);
     if (wblock == 0) return MSP_E_UNSUPPORTED;
     const int muc_len = walk_muc_len(k);
-    const int S = walk_row_stride(dimp);
+    const int S = walk_row_stride(dimp, wblock);
     MSP_TRY(c->g_bh.ensure((size_t)k * S * sizeof(double)));
     MSP_TRY(c->g_muc.ensure((size_t)muc_len * sizeof(double)));
     MSP_TRY(c->g_coff.ensure((size_t)(k + 2) * sizeof(int)));
-    MSP_TRY(launch_walk_prep(k, dim, dimp, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->g_bh.as<double>(),
+    MSP_TRY(launch_walk_prep(k, dim, dimp, wblock, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->g_bh.as<double>(),
                              c->g_muc.as<double>(), c->g_coff.as<int>(), st));
     const int64_t nwalk = (int64_t)c->num_cus * wblock;
     MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));

@@ -28,8 +28,7 @@ struct Frontier {
 };
 
 // Width of the padded projected vector held per lane, and of records.
-constexpr int kRotMax = 14;   // largest lane rotation (columns), see walk.hip
-constexpr int kWsTail = 16;   // WS = DIMP + kWsTail
+constexpr int kWsTail = 16;   // WS = DIMP + kWsTail: covers the one-wave walker's largest column rotation (14)
 
 inline int dimp_for(int dim) {
     // supported compile-time widths (even, ascending)
@@ -123,10 +122,11 @@ struct WalkArgs {
     int hoelder, onedir;
 };
 hipError_t launch_walk(const WalkArgs &a, int dimp, int block, int num_cus, hipStream_t st);
-hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
-                            double *g_muc, int *g_coff, hipStream_t st);
+// block: threads per workgroup of the walk that follows (it fixes the row layout)
+hipError_t launch_walk_prep(int k, int dim, int dimp, int block, const double *bhat, const double *mu,
+                            double *g_bh, double *g_muc, int *g_coff, hipStream_t st);
 size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len);
-__host__ __device__ int walk_row_stride(int dimp);
+__host__ __device__ int walk_row_stride(int dimp, int block);  // doubles per LDS row
 int walk_muc_len(int k);
 int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
 int walk_max_level(int dimp, int k);         // largest split level whose walker fits in LDS

@@ -51,14 +51,17 @@ constexpr int kRot = 2;  // rotation granule (columns): 128-bit reads
 #ifndef MSP_WALK_INNER
 #define MSP_WALK_INNER 1024
 #endif
-#ifndef MSP_WALK_ROTS
-#define MSP_WALK_ROTS 8
-#endif
-#ifndef MSP_WALK_ROWALIGN
-#define MSP_WALK_ROWALIGN 16
-#endif
-constexpr int kRowWrap = 2 * (MSP_WALK_ROTS - 1);  // wrap-around columns of a row: the largest rotation
-constexpr int kRowAlign = MSP_WALK_ROWALIGN;        // row stride granule (doubles)
+// Row layout in LDS.  The two-wave variant rotates each lane's columns by
+// 2 (lane mod 16) and aligns every row to 1 KB, so 16 lanes reading 16
+// arbitrary rows hit 16 distinct 16-byte bank groups; the one-wave variant
+// rotates by 2 (lane mod 8) with 128-byte rows (a stored root's w carries
+// padding for 8 rotations only).
+__host__ __device__ constexpr int row_rots(bool two_wave) { return two_wave ? 16 : 8; }
+__host__ __device__ constexpr int row_wrap(bool two_wave) { return 2 * (row_rots(two_wave) - 1); }
+__host__ __device__ constexpr int row_align(bool two_wave) { return two_wave ? 128 : 16; }
+__host__ __device__ constexpr int row_stride(int dimp, bool two_wave) {
+    return ((dimp + row_wrap(two_wave) + row_align(two_wave) - 1) / row_align(two_wave)) * row_align(two_wave);
+}
 
 __device__ __forceinline__ unsigned long long wall_clock() { return wall_clock64(); }
 
@@ -113,7 +116,7 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
 
 }  // namespace
 
-__host__ __device__ int walk_row_stride(int dimp) { return ((dimp + kRowWrap + kRowAlign - 1) / kRowAlign) * kRowAlign; }
+__host__ __device__ int walk_row_stride(int dimp, int block) { return row_stride(dimp, block == 512); }
 // per-thread u row: an odd number of 8-byte words, so 16 lanes reading the
 // same word index hit 16 distinct bank pairs
 __host__ __device__ int walk_u_stride(int k) {
@@ -132,20 +135,21 @@ __host__ __device__ int walk_muc_offset(int k, int t) {
 }
 
 size_t walk_lds_bytes(int dimp, int block, int k, int L, int muc_len) {
-    const int S = walk_row_stride(dimp);
+    const int S = walk_row_stride(dimp, block);
     return sizeof(double) * ((size_t)L * S + (size_t)muc_len + (size_t)k) + sizeof(int) * (size_t)((k + 2) & ~1) +
            (size_t)walk_u_stride(k) * block;
 }
 
 // Layouts used by the walker: rotated rows (k x S) and mu by columns.
-__global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
-                                 double *g_muc, int *g_coff) {
-    const int S = walk_row_stride(dimp);
+__global__ void walk_prep_kernel(int k, int dim, int dimp, int block, const double *bhat, const double *mu,
+                                 double *g_bh, double *g_muc, int *g_coff) {
+    const int S = walk_row_stride(dimp, block);
+    const int wrap = row_wrap(block == 512);
     const int t = blockIdx.x;
     if (t < k) {
         for (int p = threadIdx.x; p < S; p += blockDim.x) {
             double v = 0.0;
-            if (p < dimp + kRowWrap) {
+            if (p < dimp + wrap) {
                 const int c = p < dimp ? p : p - dimp;
                 if (c < dim) v = bhat[(size_t)t * dim + c];
             }
@@ -180,9 +184,9 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, const double *bhat, c
 // rows in HBM (or loaded, for a root that root generation stored).
 template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
-    constexpr int S = ((DIMP + kRowWrap + kRowAlign - 1) / kRowAlign) * kRowAlign;
-    constexpr int kInner = MSP_WALK_INNER;  // most iterations of the inner loop between rare-work passes
     constexpr bool ALLROWS = BLOCK == 512;
+    constexpr int S = row_stride(DIMP, ALLROWS);
+    constexpr int kInner = MSP_WALK_INNER;  // most iterations of the inner loop between rare-work passes
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k, L = ALLROWS ? a.k : a.L, tid = threadIdx.x;
     double *const stack_base = a.stack;
@@ -202,9 +206,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     __syncthreads();
 
     const int lane = tid & 63;
-    // rotation of the lane's columns: 8 or 16 distinct rotations with every row
-    // in LDS; 8 otherwise (a stored root's w is padded for 8 only)
-    const int rot = kRot * (lane & (ALLROWS ? MSP_WALK_ROTS - 1 : 7));
+    const int rot = kRot * (lane & (row_rots(ALLROWS) - 1));  // this lane's column rotation
     int8_t *my_u = s_u + tid * KU;  // my_u[k-1-j] = u_j
     const double bound = a.bound, hfac = a.hfac, rmax_d = a.rmax_d;
     const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
@@ -693,9 +695,10 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     flush_counters();
 }
 
-hipError_t launch_walk_prep(int k, int dim, int dimp, const double *bhat, const double *mu, double *g_bh,
-                            double *g_muc, int *g_coff, hipStream_t st) {
-    hipLaunchKernelGGL(walk_prep_kernel, dim3(k), dim3(128), 0, st, k, dim, dimp, bhat, mu, g_bh, g_muc, g_coff);
+hipError_t launch_walk_prep(int k, int dim, int dimp, int block, const double *bhat, const double *mu,
+                            double *g_bh, double *g_muc, int *g_coff, hipStream_t st) {
+    hipLaunchKernelGGL(walk_prep_kernel, dim3(k), dim3(128), 0, st, k, dim, dimp, block, bhat, mu, g_bh, g_muc,
+                       g_coff);
     return hipGetLastError();
 }
 
