@@ -126,6 +126,7 @@ struct msp_ctx {
     Buf lll_desc, lll_work, batch_basis;
     Buf g_bh, g_muc, g_coff;
     Buf pool_u, pool_meta, pool_ready;
+    Buf leaf_x;  // the walkers' leaf staging rows
     long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
     // root orders
@@ -286,6 +287,7 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->pool_u.release();
     c->pool_meta.release();
     c->pool_ready.release();
+    c->leaf_x.release();
     for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->sol_u, &c->trace_x, &c->w_master,
                    &c->w_q, &c->adam_m, &c->adam_v, &c->step, &c->partial, &c->loss_acc, &c->dev_loss, &c->npos,
                    &c->sh_keys, &c->sh_keys_out, &c->sh_idx, &c->sh_perm, &c->sh_tmp})
@@ -543,6 +545,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
                              c->g_muc.as<double>(), c->g_coff.as<int>(), st));
     const int64_t nwalk = (int64_t)c->num_cus * wblock;
     MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));
+    MSP_TRY(c->leaf_x.ensure((size_t)nwalk * n));
     const int64_t ninit = np + nleft;  // roots with stored w, then prefix-only items
     const int64_t pcap = ninit + std::max<int64_t>(256 * nwalk, 1 << 22);
     if (pcap + nwalk >= (int64_t(1) << 31)) return MSP_E_UNSUPPORTED;  // walker tickets are 32-bit
@@ -592,6 +595,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.pending = &ctl->pending;
         wa.stack = c->stack.as<double>();
         wa.x_out = x_dev;
+        wa.leaf_x = c->leaf_x.as<uint8_t>();
         wa.cap = cap;
         wa.n_found = &ctl->n_found;
         wa.counters = ctl->counters;

@@ -104,6 +104,7 @@ struct WalkArgs {
     long long *pending;            // items created and not yet finished
     double *stack;                 // per walker k entries x 4 doubles
     uint8_t *x_out;
+    uint8_t *leaf_x;               // per walker n bytes: a leaf's x staged while it is checked
     int8_t *sol_u;                 // optional: u_0..u_{k-1} of each written solution (cap x k)
     int64_t cap;
     unsigned long long *n_found;

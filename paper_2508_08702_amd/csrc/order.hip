@@ -12,7 +12,7 @@
 //     the roots are taken best score first.
 // This file holds the per-root feature and label kernels, the MLP forward,
 // gradient and Adam kernels, and the sorts that turn scores into an order.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "enum_rules.h"
 #include "msp_internal.h"
@@ -441,29 +441,29 @@ __global__ void iota64_kernel(int64_t *v, int64_t n) {
 hipError_t sort_scores_desc(void *temp, size_t *temp_bytes, const float *key_in, float *key_out, int64_t *idx_in,
                             int64_t *idx_out, int64_t n, hipStream_t st) {
     if (temp == nullptr)
-        return hipcub::DeviceRadixSort::SortPairsDescending(nullptr, *temp_bytes, key_in, key_out, idx_in, idx_out,
-                                                            (int)n, 0, 32, st);
+        return rocprim::radix_sort_pairs_desc(nullptr, *temp_bytes, key_in, key_out, idx_in, idx_out, (size_t)n, 0,
+                                              32, st);
     hipLaunchKernelGGL(iota64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx_in, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairsDescending(temp, *temp_bytes, key_in, key_out, idx_in, idx_out, (int)n,
-                                                        0, 32, st);
+    return rocprim::radix_sort_pairs_desc(temp, *temp_bytes, key_in, key_out, idx_in, idx_out, (size_t)n, 0, 32,
+                                          st);
 }
 
 // Ascending sort of indices (restores depth-first order of a selection).
 hipError_t sort_idx_asc(void *temp, size_t *temp_bytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
-    return hipcub::DeviceRadixSort::SortKeys(temp, *temp_bytes, in, out, (int)n, 0, 64, st);
+    return rocprim::radix_sort_keys(temp, *temp_bytes, in, out, (size_t)n, 0, 64, st);
 }
 
 hipError_t shuffle_perm(void *temp, size_t *temp_bytes, uint32_t *keys, uint32_t *keys_out, int32_t *idx,
                         int32_t *perm, int64_t n, unsigned long long seed, int epoch, hipStream_t st) {
     if (temp == nullptr)
-        return hipcub::DeviceRadixSort::SortPairs(nullptr, *temp_bytes, keys, keys_out, idx, perm, (int)n, 0, 32, st);
+        return rocprim::radix_sort_pairs(nullptr, *temp_bytes, keys, keys_out, idx, perm, (size_t)n, 0, 32, st);
     hipLaunchKernelGGL(shuffle_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, idx, n, seed,
                        epoch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, keys, keys_out, idx, perm, (int)n, 0, 32, st);
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, keys, keys_out, idx, perm, (size_t)n, 0, 32, st);
 }
 
 }  // namespace msp

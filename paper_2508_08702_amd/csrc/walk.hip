@@ -285,12 +285,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         }
         // exact leaf test (Thm 1) and A x = d, integers only
         if (__ballot(leafpend != 0)) {
+            bool ok = false;
+            uint8_t *xs = a.leaf_x + (size_t)(blockIdx.x * BLOCK + tid) * (size_t)a.n;  // this walker's staging row
             if (leafpend && state == RUN) {
-                // v = sum_i u_i b_i exactly, one coordinate at a time.  A
-                // solution has v_n = +-r_max and, with that sign taken off,
-                // |v_j| <= r_max (Thm 1); x_j = (v_j + r_max) / (2 c_j), then
-                // A x = d is checked row by row from the x held in registers
-                // of the output row (written only once the row is accepted).
+                // v = sum_i u_i b_i exactly, each coordinate once.  A solution
+                // has v_n = +-r_max and, with that sign taken off, |v_j| <= r_max
+                // (Thm 1); x_j = (v_j + r_max) / (2 c_j) is staged, then A x = d
+                // is checked from the staged row.
                 const int64_t rmax = a.rmax;
                 my_u[k - 1] = (int8_t)u;  // u_0 joins the prefix for the reconstruction
                 auto coord = [&](int j) -> int64_t {
@@ -299,37 +300,48 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     return sv;
                 };
                 const int64_t vn = coord(a.n);
-                bool ok = vn == rmax || vn == -rmax;
+                ok = vn == rmax || vn == -rmax;
                 const int64_t sg = vn > 0 ? 1 : -1;
                 for (int j = 0; j < a.n && ok; ++j) {
                     const int64_t sv = sg * coord(j);
                     const int64_t cj2 = 2 * (a.cvec ? a.cvec[j] : 1);
                     ok = sv <= rmax && sv >= -rmax && (sv + rmax) % cj2 == 0;
+                    if (ok) xs[j] = (uint8_t)((sv + rmax) / cj2);
                 }
                 for (int mi = 0; mi < a.m && ok; ++mi) {
                     int64_t acc = 0;
-                    for (int j = 0; j < a.n; ++j) {
-                        const int64_t sv = sg * coord(j);
-                        acc += (int64_t)a.A[(size_t)mi * a.n + j] * ((sv + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
-                    }
+                    for (int j = 0; j < a.n; ++j) acc += (int64_t)a.A[(size_t)mi * a.n + j] * (int64_t)xs[j];
                     ok = acc == a.d[mi];
                 }
+            }
+            // verified rows: one slot range per wave (ballot and prefix count)
+            const unsigned long long om = __ballot(ok);
+            if (om) {
+                const int leader = __ffsll((long long)om) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) {
+                    base = atomicAdd(a.n_found, (unsigned long long)__popcll(om));
+                    if (a.mode == 1) {
+                        atomicCAS(a.t_first, 0ull, wall_clock());
+                        atomicOr(&a.flags[0], 1);
+                    }
+                }
+                base = __shfl(base, leader, 64);
                 if (ok) {
-                    const unsigned long long slot = atomicAdd(a.n_found, 1ull);
+                    const unsigned long long slot =
+                        base + (unsigned)__builtin_amdgcn_mbcnt_hi((unsigned)(om >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)om, 0));
                     if ((int64_t)slot < a.cap) {
                         if (a.sol_u) {
                             int8_t *so = a.sol_u + (size_t)slot * k;
                             for (int i = 0; i < k; ++i) so[i] = my_u[k - 1 - i];
                         }
                         uint8_t *xo = a.x_out + (size_t)slot * a.n;
-                        for (int j = 0; j < a.n; ++j)
-                            xo[j] = (uint8_t)((sg * coord(j) + rmax) / (2 * (a.cvec ? a.cvec[j] : 1)));
-                    }
-                    if (a.mode == 1) {
-                        atomicCAS(a.t_first, 0ull, wall_clock());
-                        atomicOr(&a.flags[0], 1);
+                        for (int j = 0; j < a.n; ++j) xo[j] = xs[j];
                     }
                 }
+            }
+            if (leafpend && state == RUN) {
                 my_u[k - 1] = 0;
                 advance();
             }
