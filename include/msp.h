@@ -2,8 +2,8 @@
  * msp.h -- C ABI of libmsp, a GPU (gfx950) solver for the market split
  * feasibility problem by lattice enumeration.
  *
- * Problem (paper, Section 1): given A in Z^{m x n} with entries >= 0 and
- * d in Z^m, find x in {0,1}^n with A x = d.  The method (Section 2):
+ * Problem (paper, Section 1): given A in Z^{m x n} and d in Z^m (entries of
+ * either sign, Section 2), find x in {0,1}^n with A x = d.  The method (Section 2):
  *   1. embed the problem in the lattice spanned by the n+1 columns of the
  *      (m+n+1) x (n+1) matrix of eq. (2), binary case r_max = c_i = 1,
  *      with a scale constant N (default 2^10);
@@ -234,6 +234,17 @@ int msp_enumerate_bounded(msp_ctx *ctx, int m, int n, const int32_t *A_dev, cons
                           const int32_t *r_dev, const int64_t *basis_dev, int k, int mode, int order,
                           const msp_params *p, uint8_t *x_dev, int64_t cap, int64_t *n_found,
                           msp_stats *stats, void *stream);
+
+/* General box bounds l_j <= x_j <= u_j (Section 2): the library applies the
+ * paper's substitution x := x - l, d := d - A l, r := u - l in a kernel, runs
+ * msp_reduce_bounded and msp_enumerate_bounded on the shifted problem, and
+ * writes x = x' + l.  lo_dev, hi_dev: int32 n with 1 <= u_j - l_j <= 255 and
+ * |l_j|, |u_j| <= 2^24 (MSP_E_ARG otherwise).  x_dev: int32 cap x n, rows in
+ * unspecified order.  Modes, orders, n_found, stats and errors as
+ * msp_enumerate; the reduction (with p->bkz_block) is part of the call. */
+int msp_solve_box(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
+                  const int32_t *lo_dev, const int32_t *hi_dev, int mode, int order, const msp_params *p,
+                  int32_t *x_dev, int64_t cap, int64_t *n_found, msp_stats *stats, void *stream);
 
 /* One instance of a batch: A_dev + A_off holds its m x n matrix, d_dev +
  * d_off its right-hand side, x_dev + x_off its output rows (cap x n). */

@@ -129,3 +129,39 @@ def train_set(seeds=range(4000, 4192)) -> list[Instance]:
         D = (50, 100, 200)[i % 3]
         out.append(msp_class(m, D, s))
     return out
+
+
+def signed_planted(m: int, n: int, lo: int, hi: int, seed: int) -> Instance:
+    """A ~ U[lo, hi)^{m x n} (entries of either sign), x* ~ U{0,1}^n,
+    d = A x* (the paper allows negative entries in A and d, Section 2)."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(lo, hi, size=(m, n), dtype=np.int32)
+    x = rng.integers(0, 2, size=n).astype(np.uint8)
+    d = A.astype(np.int64) @ x.astype(np.int64)
+    return Instance(A=np.ascontiguousarray(A), d=d.astype(np.int64), x_planted=x, seed=seed, D=hi - lo)
+
+
+@dataclass(frozen=True)
+class BoxInstance:
+    """A x = d with l_j <= x_j <= u_j (integers); x_planted lies in the box."""
+
+    A: np.ndarray      # int32 (m, n)
+    d: np.ndarray      # int64 (m,)
+    lo: np.ndarray     # int32 (n,)
+    hi: np.ndarray     # int32 (n,)
+    x_planted: np.ndarray  # int64 (n,)
+    seed: int
+
+
+def box_planted(m: int, n: int, a_lo: int, a_hi: int, l_lo: int, l_hi: int, r_max: int, seed: int) -> BoxInstance:
+    """A ~ U[a_lo, a_hi)^{m x n}, lower bounds l ~ U[l_lo, l_hi), widths
+    r ~ U{1..r_max}, upper bounds u = l + r, x* ~ U{l..u} per coordinate,
+    d = A x*."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(a_lo, a_hi, size=(m, n), dtype=np.int32)
+    lo = rng.integers(l_lo, l_hi, size=n).astype(np.int32)
+    r = rng.integers(1, r_max + 1, size=n).astype(np.int32)
+    hi = (lo + r).astype(np.int32)
+    x = lo.astype(np.int64) + np.array([rng.integers(0, int(ri) + 1) for ri in r], dtype=np.int64)
+    d = A.astype(np.int64) @ x
+    return BoxInstance(A=np.ascontiguousarray(A), d=d, lo=lo, hi=hi, x_planted=x, seed=seed)

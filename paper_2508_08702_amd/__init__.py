@@ -44,7 +44,7 @@ EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_solve_first", "msp_strerror",
     "msp_reduce_bounded", "msp_enumerate_bounded", "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
-    "msp_model_grad", "msp_train_params_default", "msp_model_train", "msp_reduce_noalloc",
+    "msp_model_grad", "msp_train_params_default", "msp_model_train", "msp_reduce_noalloc", "msp_solve_box",
 )
 
 
@@ -123,6 +123,9 @@ def _load() -> C.CDLL:
     lib.msp_enumerate_bounded.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, i64,
                                           C.POINTER(i64), C.POINTER(Stats), vp]
     lib.msp_enumerate_bounded.restype = i32
+    lib.msp_solve_box.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, i32, C.POINTER(Params), vp, i64,
+                                  C.POINTER(i64), C.POINTER(Stats), vp]
+    lib.msp_solve_box.restype = i32
     lib.msp_autotune.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params),
                                  C.POINTER(Params), C.POINTER(TunePoint), C.POINTER(i32), vp]
     lib.msp_autotune.restype = i32
@@ -225,10 +228,10 @@ def _check_out(out, n: int, name: str = "out") -> int:
     return so[0]
 
 
-def _check_bounds(r, n: int) -> None:
-    sr = _shape_of(r, "r")
+def _check_bounds(r, n: int, name: str = "r") -> None:
+    sr = _shape_of(r, name)
     if len(sr) != 1 or sr[0] != n:
-        raise ValueError(f"r must hold n = {n} entries, got shape {sr}")
+        raise ValueError(f"{name} must hold n = {n} entries, got shape {sr}")
 
 
 def _check_features(feat, label=None) -> int:
@@ -646,5 +649,30 @@ def msp_enumerate_bounded(ctx: Context, A: torch.Tensor, d: torch.Tensor, r: tor
                                      out.data_ptr(), int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
     if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
         raise MspError(rc, "msp_enumerate_bounded")
+    rows = min(nf.value, cap)
+    return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())
+
+
+def msp_solve_box(ctx: Context, A: torch.Tensor, d: torch.Tensor, lo: torch.Tensor, hi: torch.Tensor, *,
+                  mode: int = MSP_ALL, order: int = MSP_PLAIN, params: Params | None = None,
+                  cap: int = 1 << 16, raise_on_error: bool = True) -> EnumResult:
+    """All (or the first) integer x with A x = d and lo <= x <= hi (int32
+    device tensors of n entries, 1 <= hi - lo <= 255); rows are int32."""
+    m, n = _check_instance(A, d)
+    _check_bounds(lo, n, "lo")
+    _check_bounds(hi, n, "hi")
+    dev = ctx.device
+    ap = _dev_ptr(A, torch.int32, dev, "A")
+    dp = _dev_ptr(d, torch.int64, dev, "d")
+    lp = _dev_ptr(lo, torch.int32, dev, "lo")
+    hp = _dev_ptr(hi, torch.int32, dev, "hi")
+    out = torch.zeros((max(cap, 1), n), dtype=torch.int32, device=dev)
+    p = params if params is not None else msp_params_default()
+    nf = C.c_int64(0)
+    st = Stats()
+    rc = lib().msp_solve_box(ctx.handle, m, n, ap, dp, lp, hp, int(mode), int(order), C.byref(p), out.data_ptr(),
+                             int(cap), C.byref(nf), C.byref(st), _stream_handle(dev))
+    if rc not in (MSP_OK, MSP_E_CAPACITY, MSP_E_TIMEOUT) and raise_on_error:
+        raise MspError(rc, "msp_solve_box")
     rows = min(nf.value, cap)
     return EnumResult(x=out[:rows], n_found=nf.value, status=rc, stats=st.as_dict())

@@ -127,6 +127,7 @@ struct msp_ctx {
     Buf g_bh, g_muc, g_coff;
     Buf pool_u, pool_meta, pool_ready;
     Buf leaf_x;  // the walkers' leaf staging rows
+    Buf box_d, box_r, box_basis, box_x, box_st;  // msp_solve_box: shifted problem and its rows
     long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
     // root orders
@@ -288,6 +289,7 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->pool_meta.release();
     c->pool_ready.release();
     c->leaf_x.release();
+    for (Buf *b : {&c->box_d, &c->box_r, &c->box_basis, &c->box_x, &c->box_st}) b->release();
     for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->sol_u, &c->trace_x, &c->w_master,
                    &c->w_q, &c->adam_m, &c->adam_v, &c->step, &c->partial, &c->loss_acc, &c->dev_loss, &c->npos,
                    &c->sh_keys, &c->sh_keys_out, &c->sh_idx, &c->sh_perm, &c->sh_tmp})
@@ -1119,6 +1121,40 @@ int msp_enumerate_bounded(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
                           c->cvec.as<int64_t>(), rmax);
     return enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, mode, order, p, x_dev, cap, n_found, stats, stream,
                           nullptr, c->cvec.as<int64_t>(), rmax);
+}
+
+int msp_solve_box(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev, const int32_t *lo_dev,
+                  const int32_t *hi_dev, int mode, int order, const msp_params *p, int32_t *x_dev, int64_t cap,
+                  int64_t *n_found, msp_stats *stats, void *stream) {
+    if (!c || !A_dev || !d_dev || !lo_dev || !hi_dev || !n_found || cap < 0 || (cap > 0 && !x_dev)) return MSP_E_ARG;
+    if (m < 1 || n < 1 || m > n || n > MSP_MAX_N) return MSP_E_ARG;
+    *n_found = 0;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    MSP_TRY(c->box_d.ensure((size_t)m * sizeof(int64_t)));
+    MSP_TRY(c->box_r.ensure((size_t)n * sizeof(int32_t)));
+    MSP_TRY(c->box_basis.ensure((size_t)(n + 1) * (n + 1) * sizeof(int64_t)));
+    MSP_TRY(c->box_x.ensure((size_t)std::max<int64_t>(cap, 1) * n));
+    MSP_TRY(c->box_st.ensure(sizeof(int)));
+    // x := x - l, d := d - A l, r := u - l (Section 2)
+    MSP_TRY(launch_box_setup(m, n, A_dev, d_dev, lo_dev, hi_dev, c->box_d.as<int64_t>(), c->box_r.as<int32_t>(),
+                             c->box_st.as<int>(), st));
+    int bad = 0;
+    MSP_TRY(hipMemcpyAsync(&bad, c->box_st.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    if (bad) return MSP_E_ARG;
+    int k = 0;
+    int rc = msp_reduce_bounded(c, m, n, A_dev, c->box_d.as<int64_t>(), c->box_r.as<int32_t>(), p,
+                                c->box_basis.as<int64_t>(), &k, stream);
+    if (rc != MSP_OK) return rc;
+    rc = msp_enumerate_bounded(c, m, n, A_dev, c->box_d.as<int64_t>(), c->box_r.as<int32_t>(),
+                               c->box_basis.as<int64_t>(), k, mode, order, p, c->box_x.as<uint8_t>(), cap, n_found,
+                               stats, stream);
+    if (rc != MSP_OK && rc != MSP_E_CAPACITY && rc != MSP_E_TIMEOUT) return rc;
+    // x = x' + l for every row written
+    MSP_TRY(launch_box_shift(std::min<int64_t>(*n_found, cap), n, c->box_x.as<uint8_t>(), lo_dev, x_dev, st));
+    MSP_TRY(hipStreamSynchronize(st));
+    return rc;
 }
 
 int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,

@@ -253,4 +253,9 @@ struct LllDesc {
 hipError_t launch_bounds_scale(const int32_t *r, int n, int64_t *cvec, long long *rmax, hipStream_t st);
 size_t lll_lds_bytes(int n);
 
+// ---- box bounds (box.hip) ----
+hipError_t launch_box_setup(int m, int n, const int32_t *A, const int64_t *d, const int32_t *lo, const int32_t *hi,
+                            int64_t *d_out, int32_t *r_out, int *status, hipStream_t st);
+hipError_t launch_box_shift(int64_t rows, int n, const uint8_t *xs, const int32_t *lo, int32_t *x, hipStream_t st);
+
 }  // namespace msp
