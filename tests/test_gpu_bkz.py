@@ -69,3 +69,18 @@ def test_bkz_argument_check(M, ctx):
     inst = mi.msp_class(5, 100, 3)
     with pytest.raises(M.MspError):
         M.msp_reduce(ctx, _dev(inst.A), _dev(inst.d), M.msp_params_default(bkz_block=1))
+
+
+@pytest.mark.parametrize("m,D,seed,beta", [(4, 100, 3, 10), (5, 100, 11, 8), (6, 100, 2000, 6)])
+def test_bkz_output_satisfies_the_block_condition(M, ctx, m, D, seed, beta):
+    """With tours enough to converge, no projected block of the GPU's BKZ
+    basis holds a vector shorter than 0.999 ||b_hat_j||^2 (the insertion
+    threshold), checked by the oracle's exact block enumeration; the LLL
+    basis of the same instance violates it (so the check has teeth)."""
+    from oracle import bkz as K
+    inst = mi.msp_class(m, D, seed)
+    A, d = _dev(inst.A), _dev(inst.d)
+    B0 = M.msp_reduce(ctx, A, d).cpu().numpy()
+    B1 = M.msp_reduce(ctx, A, d, M.msp_params_default(bkz_block=beta, bkz_tours=64)).cpu().numpy()
+    assert K.bkz_violations(B0, beta)
+    assert K.bkz_violations(B1, beta) == []
