@@ -45,7 +45,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for a
 # 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
 # valid only for the kernel source they were taken on.
-WALK_TRAFFIC = {}
+WALK_TRAFFIC = {
+    ("m9-1", 0): {"bytes": 7.618e12,
+                  "sha256": "285965cbd423b22d3be769ba7fbf19c628083d855af25e590e212cea9354597f",
+                  "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
+}
 
 
 def walk_source_hash() -> str:
@@ -292,15 +296,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step(None)
+        print(f"  warm-up step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     rec = []
     t0 = time.perf_counter()
     nodes = 0
-    for _ in range(args.steps):
+    for i in range(args.steps):
         n_, _e = step(rec)
         nodes += n_
+        print(f"  timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
