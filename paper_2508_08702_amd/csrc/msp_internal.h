@@ -215,7 +215,7 @@ hipError_t launch_permute_cols(const int32_t *A, int m, int n, const int32_t *pe
                                hipStream_t st);
 hipError_t launch_unpermute_rows(const uint8_t *xc, int64_t rows, int n, const int32_t *perm, uint8_t *x,
                                  hipStream_t st);
-size_t bkz_lds_bytes(int k);
+__host__ __device__ size_t bkz_lds_bytes(int k);
 
 // Per-instance fields are read as base[i * stride] (in 4-byte units), so a
 // packed array of descriptor structs serves as the per-instance arrays.
