@@ -32,6 +32,14 @@ __device__ __forceinline__ long long gram_at(const long long *G, int i, int j) {
     return i >= j ? G[tri(i, j)] : G[tri(j, i)];
 }
 
+// Broadcast of lane src's double to the whole wave (src uniform).
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
@@ -107,29 +115,189 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
     }
     __syncthreads();
 
-    // GS row k from the exact Gram row (forward substitution, lanes own j)
+    // GS row k from the exact Gram row, column by column (forward
+    // substitution): r_ki = G_ki - sum_{j<i} mu_ij r_kj, mu_ki = r_ki / B_i.
+    // Lane l keeps the running sum acc_l = sum_{j<i} mu_lj r_kj for its
+    // columns l and l + 64; at column i the owner's r_ki is broadcast with a
+    // readlane and every later column adds mu_li r_ki (a zero coefficient for
+    // the others leaves their sums as they are).  The divisions and the sum
+    // for B_k follow the loop, one per column in parallel.
+    constexpr int kAhead = 8;
     auto gs_row = [&](int k) {
-        double acc0 = 0.0, acc1 = 0.0;  // sum_{i<j} mu_ji r_ki for j = lane, lane + 64
-        for (int i = 0; i < k; ++i) {
-            const int owner = i & 63;
-            double r = 0.0;
-            if (lane == owner) r = (double)gram_at(G, k, i) - (i < 64 ? acc0 : acc1);
-            r = __shfl(r, owner, 64);
-            const double mki = r / Bn[i];
-            if (lane == 0) {
-                rr[i] = r;
-                mu[k * (k - 1) / 2 + i] = mki;
+        const int j0 = lane, j1 = lane + 64;
+        const double g0 = j0 < k ? (double)gram_at(G, k, j0) : 0.0;
+        const double g1 = j1 < k ? (double)gram_at(G, k, j1) : 0.0;
+        double acc0 = 0.0, acc1 = 0.0, r0 = 0.0, r1 = 0.0;
+        for (int ib = 0; ib < k; ib += kAhead) {
+            double c0[kAhead], c1[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int i = ib + u;
+                const bool v0 = j0 > i && j0 < k, v1 = j1 > i && j1 < k;
+                c0[u] = mu[v0 ? j0 * (j0 - 1) / 2 + i : 0];
+                c1[u] = mu[v1 ? j1 * (j1 - 1) / 2 + i : 0];
+                if (!v0) c0[u] = 0.0;
+                if (!v1) c1[u] = 0.0;
             }
-            const int j0 = lane, j1 = lane + 64;
-            if (j0 > i && j0 < k) acc0 += mu[j0 * (j0 - 1) / 2 + i] * r;
-            if (j1 > i && j1 < k) acc1 += mu[j1 * (j1 - 1) / 2 + i] * r;
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int i = ib + u;
+                if (i < k) {
+                    double r;
+                    if (i < 64) {
+                        const double t = g0 - acc0;
+                        if (lane == i) r0 = t;
+                        r = bcast(t, i);
+                    } else {
+                        const double t = g1 - acc1;
+                        if (lane == i - 64) r1 = t;
+                        r = bcast(t, i - 64);
+                    }
+                    acc0 += c0[u] * r;
+                    acc1 += c1[u] * r;
+                }
+            }
         }
-        __syncthreads();
         double s = 0.0;
-        for (int i = lane; i < k; i += 64) s += mu[k * (k - 1) / 2 + i] * rr[i];
+        if (j0 < k) {
+            const double mki = r0 / Bn[j0];
+            mu[k * (k - 1) / 2 + j0] = mki;
+            s += mki * r0;
+        }
+        if (j1 < k) {
+            const double mki = r1 / Bn[j1];
+            mu[k * (k - 1) / 2 + j1] = mki;
+            s += mki * r1;
+        }
         for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) Bn[k] = (double)gram_at(G, k, k) - s;
         __syncthreads();
+    };
+
+    // One pass of size reduction of b_k against b_{k-1}, ..., b_0: for j
+    // descending, b_k -= rint(mu_kj) b_j wherever |mu_kj| > 0.51, with the mu
+    // row updated after each subtraction (mu_ki -= q mu_ji for i < j, mu_kj -=
+    // q).  The mu row is held in registers and the next column is the highest
+    // one over the threshold, found by ballot; the multiples q_j are collected
+    // and the basis row and the Gram row are updated once at the end:
+    //   b_k' = b_k - sum_j q_j b_j,  G_ki' = G_ki - sum_j q_j G_ji (i != k),
+    //   G_kk' = G_kk - sum_j q_j (G_kj + G_kj').
+    // The new row's squared length, B_k + sum_i mu_ki'^2 B_i, bounds every
+    // updated entry; while it is below 2^61 the exact values fit in int64 and
+    // wrapping int64 arithmetic computes them exactly, and the exact diagonal
+    // entry is then checked against the estimate and against 2^62.  Returns
+    // whether anything was subtracted; sets st = -10 for a multiple beyond the
+    // exact integer range.
+    auto reduce_pass = [&](int k, int &stat) -> bool {
+        const int j0 = lane, j1 = lane + 64;
+        const int rk = k * (k - 1) / 2;
+        double m0 = j0 < k ? mu[rk + j0] : 0.0;
+        double m1 = j1 < k ? mu[rk + j1] : 0.0;
+        long long q0 = 0, q1 = 0;
+        int top = k;
+        for (;;) {
+            const unsigned long long b1 = __ballot(j1 < top && !(fabs(m1) <= 0.51));
+            const unsigned long long b0 = __ballot(j0 < top && !(fabs(m0) <= 0.51));
+            int j;
+            double mj;
+            if (b1) {
+                j = 64 + 63 - __clzll(b1);
+                mj = bcast(m1, j - 64);
+            } else if (b0) {
+                j = 63 - __clzll(b0);
+                mj = bcast(m0, j);
+            } else {
+                break;
+            }
+            if (!(fabs(mj) < 9.0e15)) {  // NaN or beyond exact integer range
+                stat = -10;
+                return true;
+            }
+            const long long q = (long long)rint(mj);
+            const double qd = (double)q;
+            const int rj = j * (j - 1) / 2;
+            if (j0 < j) m0 -= qd * mu[rj + j0];
+            if (j1 < j) m1 -= qd * mu[rj + j1];
+            if (j0 == j) m0 -= qd, q0 = q;
+            if (j1 == j) m1 -= qd, q1 = q;
+            top = j;
+        }
+        if (top == k) return false;
+        // basis row (global memory; lane owns columns lane + 64 t) and Gram row
+        uint64_t bk[kMaxCols];
+#pragma unroll
+        for (int c4 = 0; c4 < kMaxCols; ++c4) {
+            const int c = lane + c4 * kLanes;
+            bk[c4] = c < len ? (uint64_t)B[(size_t)k * len + c] : 0;
+        }
+        for (int h = 0; h < 2; ++h) {
+            unsigned long long nz = __ballot((h ? q1 : q0) != 0);
+            while (nz) {
+                const int bit = __ffsll(nz) - 1;
+                nz &= nz - 1;
+                const int j = bit + h * 64;
+                const long long qv = h ? q1 : q0;
+                const uint64_t q = ((uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(qv >> 32), bit) << 32) |
+                                   (unsigned)__builtin_amdgcn_readlane((int)qv, bit);
+#pragma unroll
+                for (int c4 = 0; c4 < kMaxCols; ++c4) {
+                    const int c = lane + c4 * kLanes;
+                    if (c < len) bk[c4] -= q * (uint64_t)B[(size_t)j * len + c];
+                }
+            }
+        }
+        double est = 0.0;
+        if (j0 < k) est = m0 * m0 * Bn[j0];
+        if (j1 < k) est += m1 * m1 * Bn[j1];
+        for (int o = 32; o >= 1; o >>= 1) est += __shfl_xor(est, o, 64);
+        est += Bn[k];
+        bool bad = !(est < 0x1p61);
+        uint64_t gold[2], gnew[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + h * 64;
+            gold[h] = (i < nv && i != k) ? (uint64_t)gram_at(G, k, i) : 0;
+            gnew[h] = gold[h];
+        }
+        for (int h = 0; h < 2; ++h) {
+            unsigned long long nz = __ballot((h ? q1 : q0) != 0);
+            while (nz) {
+                const int bit = __ffsll(nz) - 1;
+                nz &= nz - 1;
+                const int j = bit + h * 64;
+                const long long qv = h ? q1 : q0;
+                const uint64_t q = ((uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(qv >> 32), bit) << 32) |
+                                   (unsigned)__builtin_amdgcn_readlane((int)qv, bit);
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const int i = lane + g * 64;
+                    const uint64_t gj = (uint64_t)gram_at(G, j, i < nv ? i : 0);
+                    if (i < nv && i != k) gnew[g] -= q * gj;
+                }
+            }
+        }
+        uint64_t dsum = 0;
+        if (q0) dsum += (uint64_t)q0 * (gold[0] + gnew[0]);
+        if (q1) dsum += (uint64_t)q1 * (gold[1] + gnew[1]);
+        for (int o = 32; o >= 1; o >>= 1) dsum += (uint64_t)__shfl_xor((long long)dsum, o, 64);
+        const long long nd = (long long)((uint64_t)gram_at(G, k, k) - dsum);
+        if (nd <= 0 || nd > (1ll << 62) || fabs((double)nd - est) > 0.5 * est + 1024.0) bad = true;
+        __syncthreads();
+#pragma unroll
+        for (int c4 = 0; c4 < kMaxCols; ++c4) {
+            const int c = lane + c4 * kLanes;
+            if (c < len) B[(size_t)k * len + c] = (long long)bk[c4];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + h * 64;
+            if (i < nv && i != k) G[i >= k ? tri(i, k) : tri(k, i)] = (long long)gnew[h];
+            if (i < k) mu[rk + i] = h ? m1 : m0;
+        }
+        if (lane == 0) G[tri(k, k)] = nd;
+        if (__ballot(bad) && lane == 0) sflag[0] = 1;
+        __syncthreads();
+        return true;
     };
 
     if (lane == 0) Bn[0] = (double)G[0];
@@ -146,60 +314,8 @@ __global__ void __launch_bounds__(kLanes) lll_kernel(LllArgs a) {
         gs_row(k);
         // lazy size reduction: reduce, recompute the GS row, until stable
         for (int round = 0; round < 64; ++round) {
-            bool any = false;
-            for (int j = k - 1; j >= 0; --j) {
-                const double mkj = mu[k * (k - 1) / 2 + j];
-                if (!(fabs(mkj) <= 0.51)) {
-                    if (!(fabs(mkj) < 9.0e15)) {  // NaN or beyond exact integer range
-                        st = -10;
-                        break;
-                    }
-                    const long long q = (long long)rint(mkj);
-                    any = true;
-                    const double qa = fabs((double)q);
-                    // basis row: b_k -= q b_j (exact; magnitudes estimated first)
-                    for (int c4 = 0; c4 < kMaxCols; ++c4) {
-                        const int c = lane + c4 * kLanes;
-                        if (c >= len) continue;
-                        const long long bj = B[(size_t)j * len + c];
-                        if (qa * fabs((double)bj) > 1.0e15) {
-                            sflag[0] = 1;
-                            continue;
-                        }
-                        const long long nvv = B[(size_t)k * len + c] - q * bj;
-                        if (nvv > (1ll << 50) || nvv < -(1ll << 50)) sflag[0] = 1;
-                        B[(size_t)k * len + c] = nvv;
-                    }
-                    // Gram: G_kk' = G_kk - 2q G_kj + q^2 G_jj, G_ki' = G_ki - q G_ji (i != k);
-                    // every lane reads the old values before any lane writes
-                    const long long gkj = gram_at(G, k, j), gjj = gram_at(G, j, j), gkk = gram_at(G, k, k);
-                    const double est = fabs((double)gkk) + 2.0 * qa * fabs((double)gkj) + qa * qa * fabs((double)gjj);
-                    if (est > 4.0e18) sflag[0] = 1;
-                    long long newv0 = 0, newv1 = 0;
-                    const int i0 = lane, i1 = lane + 64;
-                    if (i0 < nv && i0 != k) {
-                        const long long gji = gram_at(G, j, i0);
-                        if (qa * fabs((double)gji) > 4.0e18) sflag[0] = 1;
-                        newv0 = gram_at(G, k, i0) - q * gji;
-                    }
-                    if (i1 < nv && i1 != k) {
-                        const long long gji = gram_at(G, j, i1);
-                        if (qa * fabs((double)gji) > 4.0e18) sflag[0] = 1;
-                        newv1 = gram_at(G, k, i1) - q * gji;
-                    }
-                    __syncthreads();
-                    if (i0 < nv && i0 != k) G[i0 >= k ? tri(i0, k) : tri(k, i0)] = newv0;
-                    if (i1 < nv && i1 != k) G[i1 >= k ? tri(i1, k) : tri(k, i1)] = newv1;
-                    if (lane == 0 && est <= 4.0e18) G[tri(k, k)] = gkk - 2 * q * gkj + q * q * gjj;
-                    // mu row k: mu_ki -= q mu_ji (i < j), mu_kj -= q
-                    const double qd = (double)q;
-                    for (int i = lane; i < j; i += 64) mu[k * (k - 1) / 2 + i] -= qd * mu[j * (j - 1) / 2 + i];
-                    if (lane == 0) mu[k * (k - 1) / 2 + j] -= qd;
-                    __syncthreads();
-                }
-            }
+            if (!reduce_pass(k, st)) break;
             if (st) break;
-            if (!any) break;
             gs_row(k);
         }
         if (st) break;
