@@ -131,7 +131,7 @@ struct msp_ctx {
     long long last_lll_iters = 0;
     hipEvent_t ev[8] = {};
     // root orders
-    Buf feat, key, key_out, idx_in, sort_tmp;
+    Buf feat, key, key_out, idx_in, sort_tmp, scan_tmp;
     Buf left_u, left_meta, top_idx;  // refinement: stage leftovers, best-node indices
     Buf cvec, rmax;                  // bounded variables: c_j and r_max of the last bounds
     Buf bkz_out, bkz_save;           // BKZ status words and the LLL basis kept for a fallback
@@ -290,7 +290,7 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->pool_ready.release();
     c->leaf_x.release();
     for (Buf *b : {&c->box_d, &c->box_r, &c->box_basis, &c->box_x, &c->box_st}) b->release();
-    for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->sol_u, &c->trace_x, &c->w_master,
+    for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->scan_tmp, &c->sol_u, &c->trace_x, &c->w_master,
                    &c->w_q, &c->adam_m, &c->adam_v, &c->step, &c->partial, &c->loss_acc, &c->dev_loss, &c->npos,
                    &c->sh_keys, &c->sh_keys_out, &c->sh_idx, &c->sh_perm, &c->sh_tmp})
         b->release();
@@ -385,6 +385,11 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     if (refine) MSP_TRY(c->fr[2].ensure(fcap, k, ws));
     MSP_TRY(c->counts.ensure((size_t)fcap * sizeof(int64_t)));
     MSP_TRY(c->offs.ensure((size_t)fcap * sizeof(int64_t)));
+    {
+        size_t tb = 0;
+        MSP_TRY(launch_scan(nullptr, &tb, c->counts.as<int64_t>(), c->offs.as<int64_t>(), fcap, &ctl->total, st));
+        MSP_TRY(c->scan_tmp.ensure(tb > 0 ? tb : 1));
+    }
     MSP_TRY(hipEventRecord(c->ev[2], st));
     MSP_TRY(launch_frontier_init(c->fr[0].view(), k, ws, st));
     // the walker keeps rows b_hat_0 .. b_hat_{L-1} in LDS: split at least this deep
@@ -421,7 +426,9 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             ea.counters = ctl->counters;
             ea.flags = ctl->flags;
             MSP_TRY(launch_expand_count(ea, st));
-            MSP_TRY(launch_scan(c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total, st));
+            size_t tb = c->scan_tmp.cap;
+            MSP_TRY(launch_scan(c->scan_tmp.p, &tb, c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total,
+                                st));
             int64_t total = 0;
             MSP_TRY(hipMemcpyAsync(&total, &ctl->total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             MSP_TRY(hipStreamSynchronize(st));

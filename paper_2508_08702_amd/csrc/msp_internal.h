@@ -68,7 +68,10 @@ hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_expand_write(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_frontier_init(Frontier f, int k, int ws, hipStream_t st);
 // exclusive prefix sum of counts[0..n) into offs, total into *total
-hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t *total, hipStream_t st);
+// Exclusive scan of counts[0..n) into offs and their sum into *total (device).
+// temp == nullptr: only sets *temp_bytes, the scratch the scan needs for n.
+hipError_t launch_scan(void *temp, size_t *temp_bytes, const int64_t *counts, int64_t *offs, int64_t n,
+                       int64_t *total, hipStream_t st);
 
 // Work-item pool of the walker: item i = (level T, prefix u_{T+1..k-1},
 // zig-zag continuation at level T).

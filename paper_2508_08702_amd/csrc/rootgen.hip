@@ -6,10 +6,12 @@
 // thread per parent, runs the level-t rules of Algorithm 1: zig-zag values
 // around the centre, the l2 bound, the Hoelder test and the one-direction
 // cut.  Every candidate that passes both tests is an expanded node of level t.
-// A count pass, an exclusive scan and a write pass store the children of
+// A count pass, an exclusive scan (rocPRIM) and a write pass store the children of
 // parent p contiguously after those of parent p-1, each parent's children in
 // zig-zag order -- so every level of the frontier is in depth-first order, and
 // the last frontier is the root queue in the order sequential DFS meets it.
+#include <rocprim/device/device_scan.hpp>
+
 #include "enum_rules.h"
 #include "msp_internal.h"
 
@@ -104,31 +106,9 @@ __global__ void frontier_init_kernel(Frontier f, int k, int ws) {
     }
 }
 
-// Exclusive scan by one 1024-thread workgroup: thread i sums a contiguous
-// segment, the segment sums are scanned in LDS, and each thread writes its
-// segment's offsets.
-__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *counts, int64_t *offs, int64_t n,
-                                                    int64_t *total) {
-    __shared__ int64_t part[1024];
-    const int64_t seg = (n + 1023) / 1024;
-    const int64_t lo = (int64_t)threadIdx.x * seg;
-    const int64_t hi = lo + seg < n ? lo + seg : n;
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += counts[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (int64_t i = lo; i < hi; ++i) {
-        offs[i] = run;
-        run += counts[i];
-    }
-    if (threadIdx.x == 1023) *total = part[1023];
+// total = offs[n-1] + counts[n-1] after the exclusive scan
+__global__ void scan_total_kernel(const int64_t *counts, const int64_t *offs, int64_t n, int64_t *total) {
+    if (threadIdx.x == 0) *total = n > 0 ? offs[n - 1] + counts[n - 1] : 0;
 }
 
 // Root generation's last frontier becomes the first pool items: level L-1,
@@ -220,8 +200,17 @@ hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool,
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const int64_t *counts, int64_t *offs, int64_t n, int64_t *total, hipStream_t st) {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, counts, offs, n, total);
+hipError_t launch_scan(void *temp, size_t *temp_bytes, const int64_t *counts, int64_t *offs, int64_t n,
+                       int64_t *total, hipStream_t st) {
+    if (!temp)
+        return rocprim::exclusive_scan(nullptr, *temp_bytes, counts, offs, (int64_t)0, (size_t)n,
+                                       rocprim::plus<int64_t>(), st);
+    if (n > 0) {
+        hipError_t e = rocprim::exclusive_scan(temp, *temp_bytes, counts, offs, (int64_t)0, (size_t)n,
+                                               rocprim::plus<int64_t>(), st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(64), 0, st, counts, offs, n, total);
     return hipGetLastError();
 }
 
