@@ -212,9 +212,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     const bool hoelder = a.hoelder != 0, onedir_cut = a.onedir != 0;
     const int budget = a.budget;
     const bool dcount = a.disc_count != 0;
-    // this walker's stack: k entries of {centre, partial norm of the parent, flags, discrepancies}
+    // this walker's stack: k entries of {centre, partial norm of the parent,
+    // flags, discrepancies}, level-major (level l of walker g at (l * walkers +
+    // g) * 4).  The walker index is rebuilt from the wave's first index (one
+    // scalar) and the lane id wherever it is needed, so no per-lane address
+    // has to stay live across the inner loop.
+    // (The lane id comes from v_mbcnt in a volatile block, which the compiler
+    // can neither hoist nor keep live; entry indices fit in 32 bits: at most
+    // 128 levels x 2^17 walkers.)
+    const unsigned wave_first = __builtin_amdgcn_readfirstlane(blockIdx.x * BLOCK + (tid & ~63));
+    const unsigned walkers = gridDim.x * BLOCK;
     auto stack_at = [&](int level) -> double * {
-        return stack_base + ((size_t)(blockIdx.x * BLOCK + tid) * (size_t)k + (size_t)level) * 4;
+        unsigned ln;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+        const unsigned e = (unsigned)level * walkers + wave_first + ln;
+        return stack_base + (size_t)e * 4;
     };
 
     double w[DIMP];
