@@ -46,8 +46,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
 # valid only for the kernel source they were taken on.
 WALK_TRAFFIC = {
-    ("m9-1", 0): {"bytes": 7.618e12,
-                  "sha256": "285965cbd423b22d3be769ba7fbf19c628083d855af25e590e212cea9354597f",
+    ("m9-1", 0): {"bytes": 1.365e13,
+                  "sha256": "9cd7fd7a5dba471ba537662df8f1eb28be17421f2182ce11a242cba8c7e8ed44",
                   "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
 }
 
