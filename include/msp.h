@@ -298,7 +298,13 @@ int msp_solve_first(msp_ctx *ctx, int m, int n, const int32_t *A_dev, const int6
  * walk; device events).  *best = *base with the fastest candidate's
  * target_roots.  points (may be NULL, room for 8) receives each candidate's
  * target_roots and total milliseconds; *npoints their count.  The result set
- * never depends on the candidate; only time does. */
+ * never depends on the candidate; only time does.
+ * The context also keeps, per shape group of the tuning batch (m and the n
+ * bucket ceil(n / 16)), the candidate fastest on that group, keyed by the
+ * device architecture, the mode, m and the n bucket (a later call replaces
+ * an entry).  msp_solve_batch then uses the tuned root count for every
+ * instance of a tuned shape when p->target_roots == 0 and p->split_depth < 0
+ * (modes MSP_ALL and MSP_FIRST). */
 typedef struct {
     int32_t target_roots;
     int32_t status;          /* first non-OK status over the batch, or MSP_OK */
@@ -307,6 +313,11 @@ typedef struct {
 int msp_autotune(msp_ctx *ctx, int batch, const msp_batch_desc *desc, const int32_t *A_dev,
                  const int64_t *d_dev, int mode, int order, const msp_params *base, msp_params *best,
                  msp_tune_point *points, int *npoints, void *stream);
+
+/* The root count msp_autotune tuned for instances of shape (m, n) in `mode` on
+ * this context's device, in *target_roots; 0 if that shape was not tuned.
+ * Errors: MSP_E_ARG. */
+int msp_tune_lookup(msp_ctx *ctx, int mode, int m, int n, int *target_roots);
 
 /* ---- root traces and the root-scoring model (a project addition; none of
  * this is in the paper) ------------------------------------------------- */

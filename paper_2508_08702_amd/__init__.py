@@ -44,7 +44,7 @@ EXPORTED = (
     "msp_params_default", "msp_ctx_create", "msp_ctx_destroy", "msp_reduce",
     "msp_gram_schmidt", "msp_enumerate", "msp_solve_batch", "msp_solve_first", "msp_strerror",
     "msp_reduce_bounded", "msp_enumerate_bounded", "msp_autotune", "msp_root_trace", "msp_model_init", "msp_model_set", "msp_model_get", "msp_model_score",
-    "msp_model_grad", "msp_train_params_default", "msp_model_train", "msp_reduce_noalloc", "msp_solve_box",
+    "msp_model_grad", "msp_train_params_default", "msp_model_train", "msp_reduce_noalloc", "msp_solve_box", "msp_tune_lookup",
 )
 
 
@@ -129,6 +129,8 @@ def _load() -> C.CDLL:
     lib.msp_autotune.argtypes = [vp, i32, C.POINTER(BatchDesc), vp, vp, i32, i32, C.POINTER(Params),
                                  C.POINTER(Params), C.POINTER(TunePoint), C.POINTER(i32), vp]
     lib.msp_autotune.restype = i32
+    lib.msp_tune_lookup.argtypes = [vp, i32, i32, i32, C.POINTER(i32)]
+    lib.msp_tune_lookup.restype = i32
     lib.msp_root_trace.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.POINTER(Params), vp, vp, i64,
                                    C.POINTER(i64), C.POINTER(i64), C.POINTER(Stats), vp]
     lib.msp_root_trace.restype = i32
@@ -466,6 +468,15 @@ def msp_autotune(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order
     if rc != MSP_OK:
         raise MspError(rc, "msp_autotune")
     return best, [(pts[i].target_roots, pts[i].status, pts[i].ms) for i in range(npts.value)]
+
+
+def msp_tune_lookup(ctx: Context, m: int, n: int, *, mode: int = MSP_ALL) -> int:
+    """Root count msp_autotune chose for shape (m, n) in this context (0: not tuned)."""
+    t = C.c_int(0)
+    rc = lib().msp_tune_lookup(ctx.handle, int(mode), int(m), int(n), C.byref(t))
+    if rc != MSP_OK:
+        raise MspError(rc, "msp_tune_lookup")
+    return t.value
 
 
 def msp_solve_batch(ctx: Context, As: list, ds: list, *, mode: int = MSP_ALL, order: int = MSP_PLAIN,

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <random>
+#include <string>
 #include <vector>
 
 #include "../../include/msp.h"
@@ -129,6 +130,13 @@ struct msp_ctx {
     Buf leaf_x;  // the walkers' leaf staging rows
     Buf box_d, box_r, box_basis, box_x, box_st;  // msp_solve_box: shifted problem and its rows
     long long last_lll_iters = 0;
+    // tuned root counts (msp_autotune), keyed by (architecture, mode, m, n bucket)
+    struct Tuned {
+        std::string arch;
+        int mode, m, nbucket, target_roots;
+    };
+    std::string arch;
+    std::vector<Tuned> tuned;
     hipEvent_t ev[8] = {};
     // root orders
     Buf feat, key, key_out, idx_in, sort_tmp, scan_tmp;
@@ -237,6 +245,7 @@ int msp_ctx_create(int device, msp_ctx **out) {
         return MSP_E_DEVICE;
     }
     c->num_cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
         c->wall_khz = rate;
@@ -1019,6 +1028,22 @@ int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_
     return rc;
 }
 
+// n bucket of the tuned-root table: instances whose n differs by less than 16
+// share their tuned root count.
+static int n_bucket(int n) { return (n + 15) / 16; }
+
+static int tuned_roots(const msp_ctx *c, int mode, int m, int n) {
+    for (const auto &e : c->tuned)
+        if (e.arch == c->arch && e.mode == mode && e.m == m && e.nbucket == n_bucket(n)) return e.target_roots;
+    return 0;
+}
+
+int msp_tune_lookup(msp_ctx *c, int mode, int m, int n, int *target_roots) {
+    if (!c || !target_roots || m < 1 || n < 1) return MSP_E_ARG;
+    *target_roots = tuned_roots(c, mode, m, n);
+    return MSP_OK;
+}
+
 int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_t *A_dev, const int64_t *d_dev,
                     int mode, int order, const msp_params *pin, uint8_t *x_dev, int64_t *n_found, int32_t *status,
                     msp_stats *stats, void *stream) {
@@ -1060,9 +1085,13 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
         if (s == MSP_OK && mode == MSP_LDS)
             s = lds_search(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off, h[i].kout, order, &p,
                            x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream, nullptr, 1);
-        else if (s == MSP_OK)
+        else if (s == MSP_OK) {
+            // a root count tuned for this shape by msp_autotune, unless the caller set one
+            msp_params q = p;
+            if (q.target_roots == 0 && q.split_depth < 0) q.target_roots = tuned_roots(c, mode, e.m, e.n);
             s = enumerate_impl(c, e.m, e.n, A_dev + e.A_off, d_dev + e.d_off, bases + h[i].out_off, h[i].kout, mode,
-                               order, &p, x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream);
+                               order, &q, x_dev ? x_dev + e.x_off : nullptr, e.cap, &n_found[i], &sti, stream);
+        }
         sti.reduce_ms = reduce_ms;
         status[i] = s;
         if (stats) stats[i] = sti;
@@ -1202,6 +1231,17 @@ int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_
     MSP_TRY(c->trace_x.ensure((size_t)64 * (maxn > 0 ? maxn : 1)));
     double best_ms = -1.0;
     int best_t = 0;
+    // per shape group (m, n bucket): summed time and status of each candidate
+    std::vector<std::pair<int, int>> groups;
+    std::vector<int> gi(batch);
+    for (int i = 0; i < batch; ++i) {
+        const std::pair<int, int> key{desc[i].m, n_bucket(desc[i].n)};
+        auto it = std::find(groups.begin(), groups.end(), key);
+        gi[i] = (int)(it - groups.begin());
+        if (it == groups.end()) groups.push_back(key);
+    }
+    std::vector<double> gms((size_t)ncand * groups.size(), 0.0);
+    std::vector<int> gok((size_t)ncand * groups.size(), 1);
     for (int ci = 0; ci < ncand; ++ci) {
         msp_params q = p;
         q.target_roots = cand[ci] * c->num_cus;
@@ -1216,7 +1256,10 @@ int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_
                                          h[i].kout, mode, order, &q, c->trace_x.as<uint8_t>(), 64, &nf, &sti, stream);
             if (s != MSP_OK && s != MSP_E_CAPACITY && st_first == MSP_OK) st_first = s;
             if (s != MSP_OK && s != MSP_E_CAPACITY && s != MSP_E_TIMEOUT) return s;
-            tot += sti.rootgen_ms + sti.ordering_ms + sti.kernel_ms;
+            const double ms = sti.rootgen_ms + sti.ordering_ms + sti.kernel_ms;
+            tot += ms;
+            gms[(size_t)ci * groups.size() + gi[i]] += ms;
+            if (s != MSP_OK && s != MSP_E_CAPACITY) gok[(size_t)ci * groups.size() + gi[i]] = 0;
         }
         if (points && ci < 8) points[ci] = msp_tune_point{q.target_roots, st_first, tot};
         if (st_first == MSP_OK && (best_ms < 0.0 || tot < best_ms)) {
@@ -1226,6 +1269,26 @@ int msp_autotune(msp_ctx *c, int batch, const msp_batch_desc *desc, const int32_
     }
     if (npoints) *npoints = ncand;
     if (best_ms < 0.0) return MSP_E_TIMEOUT;  // no candidate finished every instance
+    // the fastest candidate of each shape group goes into the context's table
+    for (size_t g2 = 0; g2 < groups.size(); ++g2) {
+        int bt = 0;
+        double bms = -1.0;
+        for (int ci = 0; ci < ncand; ++ci) {
+            const size_t ix = (size_t)ci * groups.size() + g2;
+            if (gok[ix] && (bms < 0.0 || gms[ix] < bms)) {
+                bms = gms[ix];
+                bt = cand[ci] * c->num_cus;
+            }
+        }
+        if (bt == 0) continue;
+        bool found = false;
+        for (auto &e : c->tuned)
+            if (e.arch == c->arch && e.mode == mode && e.m == groups[g2].first && e.nbucket == groups[g2].second) {
+                e.target_roots = bt;
+                found = true;
+            }
+        if (!found) c->tuned.push_back({c->arch, mode, groups[g2].first, groups[g2].second, bt});
+    }
     *best = p;
     best->target_roots = best_t;
     best->split_depth = -1;

@@ -167,3 +167,31 @@ def test_autotune_picks_a_candidate_and_keeps_results(M, ctx, batch):
         assert np.array_equal(E.sort_rows(tuned.x[i].cpu().numpy()), E.sort_rows(plain.x[i].cpu().numpy()))
         for key in ("evals", "nodes", "expansions", "leaves"):
             assert tuned.stats[i][key] == plain.stats[i][key], key
+
+
+def test_tuned_roots_are_kept_per_shape_and_used_by_the_batch(M, ctx, batch):
+    """msp_autotune keeps the fastest candidate of each (m, n bucket) group of
+    its tuning batch; msp_solve_batch uses it for instances of those shapes,
+    and the results do not change."""
+    tune = mi.mixed_batch(range(3900, 3932))[:8]
+    shapes = {(i.m, i.n) for i in tune}
+    best, pts = M.msp_autotune(ctx, [_dev(i.A) for i in tune], [_dev(i.d) for i in tune],
+                               params=M.msp_params_default(time_cap_ms=60000.0))
+    cands = {p[0] for p in pts}
+    for m, n in shapes:
+        t = M.msp_tune_lookup(ctx, m, n)
+        assert t in cands, (m, n, t)
+        assert M.msp_tune_lookup(ctx, m, n, mode=M.MSP_FIRST) == 0     # only the tuned mode
+    assert M.msp_tune_lookup(ctx, 3, 20) == 0                          # a shape not in the tuning batch
+    insts = [i for i in batch if (i.m, i.n) in shapes][:6]
+    assert insts
+    tuned = _run_batch(M, ctx, insts)                                  # default params: the table applies
+    fixed = _run_batch(M, ctx, insts, params=M.msp_params_default(target_roots=4096))
+    for i, inst in enumerate(insts):
+        assert tuned.status[i] == fixed.status[i] == M.MSP_OK
+        assert tuned.stats[i]["roots"] != 0
+        assert np.array_equal(E.sort_rows(tuned.x[i].cpu().numpy()), E.sort_rows(fixed.x[i].cpu().numpy()))
+        for key in ("evals", "nodes", "expansions", "leaves"):
+            assert tuned.stats[i][key] == fixed.stats[i][key], key
+    with pytest.raises(M.MspError):
+        M.msp_tune_lookup(ctx, 0, 20)
