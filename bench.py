@@ -112,9 +112,11 @@ def parse():
 def batch_run(M, ctx, args, np, torch, mi, dev):
     """The uneven batch: 96 planted instances, m in 5..8 (drawn per
     instance), D by thirds.  Root counts are autotuned on 8 instances of the
-    disjoint tuning seeds 3900-3931 first (not timed); then one msp_solve_batch
-    call (one LLL launch for all, then each instance's enumeration) is timed
-    end to end and every returned row is checked A x = d."""
+    disjoint tuning seeds 3900-3931 first (not timed); the context keeps the
+    fastest count per shape (m, n bucket), which msp_solve_batch applies to
+    the instances of tuned shapes.  Then one msp_solve_batch call (one LLL
+    launch for all, then each instance's enumeration) is timed end to end and
+    every returned row is checked A x = d."""
     tune = mi.mixed_batch(range(3900, 3932))[:8]
     prm = M.msp_params_default(time_cap_ms=args.time_cap_ms)
     t0 = time.perf_counter()
@@ -124,10 +126,10 @@ def batch_run(M, ctx, args, np, torch, mi, dev):
     insts = mi.mixed_batch()
     As = [torch.from_numpy(i.A).to(dev) for i in insts]
     ds = [torch.from_numpy(i.d).to(dev) for i in insts]
-    M.msp_solve_batch(ctx, As, ds, params=best)  # warm-up
+    M.msp_solve_batch(ctx, As, ds, params=prm)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = M.msp_solve_batch(ctx, As, ds, params=best)
+    r = M.msp_solve_batch(ctx, As, ds, params=prm)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nodes = sum(st["nodes"] for st in r.stats)
@@ -140,6 +142,8 @@ def batch_run(M, ctx, args, np, torch, mi, dev):
     return {"instances": len(insts), "wall_ms": wall * 1e3, "nodes": nodes, "nodes_per_s": nodes / wall,
             "walk_ms_sum": kern, "solutions": int(sum(r.n_found)),
             "tuned_target_roots": best.target_roots, "tune_seconds": tune_s,
+            "tuned_per_shape": {f"m{m}_n{n}": M.msp_tune_lookup(ctx, m, n)
+                                for m, n in sorted({(i.m, i.n) for i in insts})},
             "tune_points": [{"target_roots": t, "status": s_, "ms": ms} for t, s_, ms in pts]}
 
 
