@@ -254,7 +254,8 @@ typedef struct {
 } msp_batch_desc;
 
 /* Reduce and enumerate a batch of independent instances of uneven shape
- * (Sections 1-2): one LLL launch reduces every instance (one wave each),
+ * (Sections 1-2): one LLL launch reduces every instance (one wave each); with
+ * p->bkz_block >= 2 each kernel basis is then BKZ-reduced as by msp_reduce;
  * then each instance is enumerated as by msp_enumerate on its own basis.
  * desc: host array of `batch` descriptors (offsets in elements).  Outputs
  * (host arrays of length batch): n_found[i], status[i] (an MSP_* code per

@@ -1058,6 +1058,7 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
     msp_params_default(&p);
     if (pin) p = *pin;
     if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
+    if (p.bkz_block < 0 || p.bkz_block == 1 || p.bkz_block > 40) return MSP_E_ARG;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
@@ -1072,6 +1073,12 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
     int64_t *bases = c->batch_basis.as<int64_t>();
     int rc = run_lll(c, h, A_dev, d_dev, bases, p, st);
     if (rc != MSP_OK) return rc;
+    // optional BKZ of each kernel basis (shapes differ, so one launch each)
+    std::vector<int> bkz_rc(batch, MSP_OK);
+    if (p.bkz_block >= 2)
+        for (int i = 0; i < batch; ++i)
+            if (lll_status(h[i].status) == MSP_OK)
+                bkz_rc[i] = bkz_after_lll(c, p, bases + h[i].out_off, h[i].kout, desc[i].n + 1, st);
     const double reduce_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / batch;
     // ---- steps 3-4 per instance ----
@@ -1080,6 +1087,7 @@ int msp_solve_batch(msp_ctx *c, int batch, const msp_batch_desc *desc, const int
         const msp_batch_desc &e = desc[i];
         n_found[i] = 0;
         int s = lll_status(h[i].status);
+        if (s == MSP_OK) s = bkz_rc[i];
         msp_stats sti;
         std::memset(&sti, 0, sizeof(sti));
         if (s == MSP_OK && mode == MSP_LDS)

@@ -195,3 +195,19 @@ def test_tuned_roots_are_kept_per_shape_and_used_by_the_batch(M, ctx, batch):
             assert tuned.stats[i][key] == fixed.stats[i][key], key
     with pytest.raises(M.MspError):
         M.msp_tune_lookup(ctx, 0, 20)
+
+
+def test_batch_with_bkz_keeps_the_solution_sets(M, ctx, batch):
+    """p.bkz_block applies to every instance of a batch (each kernel basis
+    BKZ-reduced after the shared LLL launch): the solution sets are those of
+    the LLL-only batch; the tree may change.  A block size of 1 is rejected."""
+    insts = [i for i in batch if i.m <= 6][:6]
+    plain = _run_batch(M, ctx, insts)
+    bkz = _run_batch(M, ctx, insts, params=M.msp_params_default(time_cap_ms=60000.0, bkz_block=8))
+    for i, inst in enumerate(insts):
+        assert plain.status[i] == bkz.status[i] == M.MSP_OK
+        assert np.array_equal(E.sort_rows(plain.x[i].cpu().numpy()), E.sort_rows(bkz.x[i].cpu().numpy()))
+        assert E.verify(inst.A, inst.d, bkz.x[i].cpu().numpy())
+    assert any(plain.stats[i]["nodes"] != bkz.stats[i]["nodes"] for i in range(len(insts)))
+    with pytest.raises(M.MspError):
+        _run_batch(M, ctx, insts[:2], params=M.msp_params_default(bkz_block=1))
