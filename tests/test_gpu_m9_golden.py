@@ -1,9 +1,9 @@
 """Full-size parity: the exhaustive GPU walk of planted m=9, n=80 instances
-(D=200 seed 4508, the benchmark's instance, and D=100 seed 4504) on the
-oracle's exact-LLL basis against the stored oracle results
-(tests/golden/m9_seed*.json, written by tests/golden/make_m9_golden.py from
-oracle/ alone: about 2e11 nodes, over an hour of CPU each): the same solution
-set and the same search counters."""
+(D=200 seed 4508, the benchmark's instance; D=100 seed 4504; D=50 seed 4500,
+six solutions) on the oracle's exact-LLL basis against the stored oracle
+results (tests/golden/m9_seed*.json, written by tests/golden/make_m9_golden.py
+from oracle/ alone: 2e11 to 5e11 nodes, one to two and a half hours of CPU
+each): the same solution set and the same search counters."""
 from __future__ import annotations
 
 import json
@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("name", ["m9_seed4508.json", "m9_seed4504.json"])
+@pytest.mark.parametrize("name", ["m9_seed4508.json", "m9_seed4504.json", "m9_seed4500.json"])
 def test_m9_exhaustive_matches_stored_oracle_run(name):
     import hashlib
 
