@@ -84,3 +84,27 @@ def test_bkz_output_satisfies_the_block_condition(M, ctx, m, D, seed, beta):
     B1 = M.msp_reduce(ctx, A, d, M.msp_params_default(bkz_block=beta, bkz_tours=64)).cpu().numpy()
     assert K.bkz_violations(B0, beta)
     assert K.bkz_violations(B1, beta) == []
+
+
+@pytest.mark.parametrize("m,n,D,seed,beta", [(6, 120, 50, 6100, 8), (12, 126, 100, 6101, 10)])
+def test_bkz_with_the_basis_in_hbm(M, ctx, m, n, D, seed, beta):
+    """k x dim int64 too large for LDS next to the Gram triangle and mu (k =
+    115 and 115 here): the kernel works on the basis in HBM.  The output spans
+    the same lattice (exact Gram determinant), lies in the kernel of the
+    extended system, and its first vector is no longer than LLL's."""
+    inst = mi.planted(m, n, D, seed)
+    k, dim = n - m + 1, n + 1
+    lds_without_basis = 8 * (k * (k + 1) // 2) + 8 * (k * (k - 1) // 2 + 1 + k) + 4 * (k + 6)
+    assert lds_without_basis <= 160 * 1024 < lds_without_basis + 8 * k * dim
+    A, d = _dev(inst.A), _dev(inst.d)
+    print(f"  bkz in HBM m={m} n={n} k={k} beta={beta}", flush=True)
+    B0 = M.msp_reduce(ctx, A, d).cpu().numpy()
+    B1 = M.msp_reduce(ctx, A, d, M.msp_params_default(bkz_block=beta)).cpu().numpy()
+    assert B1.shape == B0.shape == (k, dim)
+    assert not np.array_equal(B0, B1)          # BKZ changed the basis
+    for row in B1:
+        assert np.array_equal(inst.A.astype(np.int64) @ (row[:n] + row[n]), 2 * inst.d * row[n])
+    g0 = L.gram_schmidt_exact([[int(v) for v in r] for r in B0])
+    g1 = L.gram_schmidt_exact([[int(v) for v in r] for r in B1])
+    assert g0.d[-1] == g1.d[-1]
+    assert int(B1[0] @ B1[0]) <= int(B0[0] @ B0[0])
