@@ -85,7 +85,7 @@ struct FrontierBuf {
         return hipSuccess;
     }
     Frontier view() const {
-        return Frontier{u.as<int8_t>(), w.as<double>(), l.as<double>(), tz.as<uint8_t>(), dsc.as<uint8_t>()};
+        return Frontier{u.as<int8_t>(), w.as<double>(), l.as<double>(), tz.as<uint8_t>(), dsc.as<uint8_t>(), cap};
     }
     void release() {
         u.release();
@@ -349,7 +349,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     const int dim = n + 1;
     const int dimp = dimp_for(dim);
     if (dimp < 0) return MSP_E_UNSUPPORTED;
-    const int ws = dimp + kWsTail;
+    const int ws = dimp;  // columns of a stored projected vector
     if (p.block != 0 && p.block != 256 && p.block != 512) return MSP_E_ARG;
 
     // ---- Gram-Schmidt (step 3) ----
@@ -605,6 +605,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.pool = pool;
         wa.nroots = np;
         wa.root_w = c->fr[cur].w.as<double>();
+        wa.root_wcap = c->fr[cur].cap;
         wa.root_l = c->fr[cur].l.as<double>();
         wa.order = use_order ? c->order.as<int64_t>() : nullptr;
         wa.sol_u = sol_u;

@@ -19,16 +19,17 @@ namespace msp {
 //   dsc uint8 [cap]       discrepancies on the prefix: the sum of the ranks of
 //                         its values in their levels' value orders (limited
 //                         discrepancy search, paper Section 3), capped at 255
+// Records of one level of the frontier.  The projected vectors are stored
+// column-major: element j of record r at w[j * wcap + r] (wcap = the buffer's
+// record capacity), so a thread per record reads and writes them coalesced.
 struct Frontier {
     int8_t *u;
     double *w;
     double *l;
     uint8_t *tz;
     uint8_t *dsc;
+    int64_t wcap;
 };
-
-// Width of the padded projected vector held per lane, and of records.
-constexpr int kWsTail = 16;   // WS = DIMP + kWsTail: covers the one-wave walker's largest column rotation (14)
 
 inline int dimp_for(int dim) {
     // supported compile-time widths (even, ascending)
@@ -99,7 +100,8 @@ struct WalkArgs {
     const int64_t *d;
     Pool pool;
     int64_t nroots;                // items 0..nroots-1 come from root generation
-    const double *root_w;          // their projected vectors (frontier layout, DIMP + 16 per root)
+    const double *root_w;          // their projected vectors (frontier layout: element j of root r at
+    int64_t root_wcap;             //   root_w[j * root_wcap + r], j < DIMP)
     const double *root_l;          // their partial norms
     const int64_t *order;          // optional permutation of those (nullptr = identity)
     unsigned long long *head;      // next ticket

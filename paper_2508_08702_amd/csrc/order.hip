@@ -50,7 +50,8 @@ __global__ void root_feat_kernel(FeatArgs a) {
     if (r >= a.np) return;
     const int k = a.k, L = a.L;
     const int8_t *u = a.roots.u + r * k;
-    const double *w = a.roots.w + r * a.ws;
+    const double *w = a.roots.w + r;  // column-major: element j at w[j * wcap]
+    const int64_t wcap = a.roots.wcap;
     const double l = a.roots.l[r];
     const double R = a.R;
     double rank_sum = 0.0;
@@ -85,7 +86,7 @@ __global__ void root_feat_kernel(FeatArgs a) {
     double l1 = 0.0, linf = 0.0;
     int big = 0;
     for (int j = 0; j < a.dim; ++j) {
-        const double v = fabs(w[j]);
+        const double v = fabs(w[(size_t)j * wcap]);
         l1 += v;
         linf = v > linf ? v : linf;
         big += v > 1.0625;  // clear of +-1, a value projected coordinates often take exactly

@@ -22,9 +22,10 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ce = 0, cn = 0, cx = 0;
     if (p < a.np) {
-        const int k = a.k, dim = a.dim, t = a.t, ws = a.ws;
+        const int k = a.k, dim = a.dim, t = a.t;
         const int8_t *up = a.par.u + p * k;
-        const double *wp = a.par.w + p * ws;
+        const double *wp = a.par.w + p;  // column-major: element j at wp[j * pw]
+        const int64_t pw = a.par.wcap;
         const double lpar = a.par.l[p];
         const bool tz = a.par.tz[p] != 0;
         const int pd = a.par.dsc[p];
@@ -50,7 +51,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
             bool fail = false;
             if (a.hoelder) {
                 double h = 0.0;
-                for (int j = 0; j < dim; ++j) h += fabs(fma(x, bt[j], wp[j]));
+                for (int j = 0; j < dim; ++j) h += fabs(fma(x, bt[j], wp[(size_t)j * pw]));
                 fail = l > (a.rmax * h) * a.hfac;
             }
             if (fail) {
@@ -67,9 +68,10 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
                     if (u > 127 || u < -127) atomicOr(&a.flags[1], 1);
                     int8_t *uc = a.ch.u + slot * k;
                     for (int i = 0; i < k; ++i) uc[i] = i > t ? up[i] : (i == t ? (int8_t)u : (int8_t)0);
-                    double *wc = a.ch.w + slot * ws;
-                    for (int j = 0; j < a.dimp; ++j) wc[j] = j < dim ? fma(x, bt[j], wp[j]) : 0.0;
-                    for (int j = a.dimp; j < ws; ++j) wc[j] = wc[j - a.dimp];
+                    double *wc = a.ch.w + slot;
+                    const int64_t cw = a.ch.wcap;
+                    for (int j = 0; j < a.dimp; ++j)
+                        wc[(size_t)j * cw] = j < dim ? fma(x, bt[j], wp[(size_t)j * pw]) : 0.0;
                     a.ch.l[slot] = l;
                     a.ch.tz[slot] = (tz && u == 0) ? 1 : 0;
                     a.ch.dsc[slot] = (uint8_t)(pd + rank < 255 ? pd + rank : 255);
@@ -98,7 +100,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
 
 __global__ void frontier_init_kernel(Frontier f, int k, int ws) {
     for (int i = threadIdx.x; i < k; i += blockDim.x) f.u[i] = 0;
-    for (int j = threadIdx.x; j < ws; j += blockDim.x) f.w[j] = 0.0;
+    for (int j = threadIdx.x; j < ws; j += blockDim.x) f.w[(size_t)j * f.wcap] = 0.0;
     if (threadIdx.x == 0) {
         f.l[0] = 0.0;
         f.tz[0] = 1;
@@ -129,7 +131,7 @@ __global__ void gather_frontier_kernel(Frontier src, const int64_t *idx, int64_t
     const int lane = threadIdx.x & 63;
     if (r >= n) return;
     const int64_t s = idx[r];
-    for (int j = lane; j < ws; j += 64) dst.w[r * ws + j] = src.w[s * ws + j];
+    for (int j = lane; j < ws; j += 64) dst.w[(size_t)j * dst.wcap + r] = src.w[(size_t)j * src.wcap + s];
     for (int j = lane; j < k; j += 64) dst.u[r * k + j] = src.u[s * k + j];
     if (lane == 0) {
         dst.l[r] = src.l[s];

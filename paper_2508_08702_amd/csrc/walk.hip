@@ -496,12 +496,14 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             if (__ballot(take)) {
                 const double keep = take ? 0.0 : 1.0;
                 const double sel = (take && from_root) ? 1.0 : 0.0;
-                const double *pw = (take && from_root) ? a.root_w + it * (DIMP + kWsTail) + rot : a.g_bh + rot;
+                // register q holds column (rot + q) mod DIMP; the stored vectors
+                // are column-major (a lane without a root reads root 0 and adds 0)
+                const double *pw = a.root_w + ((take && from_root) ? it : 0);
+                const int64_t wc = a.root_wcap;
 #pragma unroll
-                for (int q = 0; q < DIMP; q += 2) {
-                    const double2 b = *reinterpret_cast<const double2 *>(pw + q);
-                    w[q] = fma(sel, b.x, w[q] * keep);
-                    w[q + 1] = fma(sel, b.y, w[q + 1] * keep);
+                for (int q = 0; q < DIMP; ++q) {
+                    const int c = rot + q < DIMP ? rot + q : rot + q - DIMP;
+                    w[q] = fma(sel, pw[(size_t)c * wc], w[q] * keep);
                 }
             }
             // a prefix-only item: centres, partial norms and w, top level first
