@@ -408,6 +408,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     // Expand the frontier in fr[cur] (np nodes of level L) one level at a
     // time into fr[other], swapping, until done(np, L) or level 1.  A level
     // that would not fit the frontier buffers is not taken.
+    bool capped = false;  // a level was left unexpanded for lack of frontier room
     auto expand = [&](int &cur, int other, int64_t &np, int &L, auto done) -> int {
         for (int t = L - 1; t >= 1; --t) {
             if (done(np, L)) break;
@@ -441,7 +442,10 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             int64_t total = 0;
             MSP_TRY(hipMemcpyAsync(&total, &ctl->total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             MSP_TRY(hipStreamSynchronize(st));
-            if (total > fcap) break;  // cannot hold this level: split above it
+            if (total > fcap) {  // cannot hold this level: split above it
+                capped = true;
+                break;
+            }
             MSP_TRY(launch_expand_write(ea, st));
             std::swap(cur, other);
             np = total;
@@ -462,6 +466,12 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         if (rc != MSP_OK) return rc;
     }
     const int L0 = L;  // highest level of any walked item: the walker's LDS rows
+    // The automatic split expanded every level down to 1 and still found fewer
+    // roots than it aimed for: the whole tree is small (a few nodes per root
+    // below level 1).  Then a grid of about two lanes per root walks it; a
+    // full grid would leave most lanes waiting while busy lanes split tiny
+    // items for them, each paying a prefix rebuild.
+    const bool small_tree = p.split_depth < 0 && L == 1 && np < target && !capped;
     const int64_t np0 = np;
     MSP_TRY(hipEventRecord(c->ev[3], st));
     c->last_cur = cur;
@@ -633,7 +643,10 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.hoelder = p.hoelder;
         wa.onedir = p.onedir;
         MSP_TRY(hipEventRecord(c->ev[4], st));
-        MSP_TRY(launch_walk(wa, dimp, wblock, c->num_cus, st));
+        int grid = c->num_cus;
+        if (small_tree && nleft == 0)
+            grid = (int)std::min<int64_t>(c->num_cus, std::max<int64_t>(1, (2 * np + wblock - 1) / wblock));
+        MSP_TRY(launch_walk(wa, dimp, wblock, grid, st));
         MSP_TRY(hipEventRecord(c->ev[5], st));
     } else {
         MSP_TRY(hipEventRecord(c->ev[4], st));
