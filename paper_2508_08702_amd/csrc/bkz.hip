@@ -7,11 +7,11 @@
 // Gram-Schmidt data (mu, beta) live in LDS.  The Gram matrix is computed from
 // the basis once; every row operation (b_i += q b_j, an exchange, a sign
 // change) then updates it exactly in O(k), and Gram-Schmidt rows are
-// recomputed from it whenever the LLL loop visits a row.  A tour visits every block
-// [j, h], h = min(j + beta, k) - 1:
-//   * lane 0 finds a shortest nonzero vector of the block's projected
-//     lattice by Schnorr-Euchner enumeration (radius 0.999 beta_j, shrunk to
-//     each shorter vector found, node cap per block);
+// recomputed from it whenever the LLL loop visits a row.  A tour visits every
+// block [j, h], h = min(j + beta, k) - 1:
+//   * the wave finds a shortest nonzero vector of the block's projected
+//     lattice by Schnorr-Euchner enumeration, one level per lane (radius
+//     0.999 beta_j, shrunk to each shorter vector found, node cap per block);
 //   * if it is shorter than b*_j, it is inserted at position j by unimodular
 //     row operations on b_j..b_h (integer, exact), and the basis is
 //     LLL-reduced again from j;
@@ -36,8 +36,9 @@ __device__ __forceinline__ double bcast(double v, int src) {
 }
 
 // Entries of the Gram diagonal stay <= 2^52, so every basis entry is at most
-// 2^26 in absolute value and every Gram entry at most 2^52: products and sums
-// of the updates below are checked for int64 overflow all the same.
+// 2^26 in absolute value and every Gram entry at most 2^52.  An update that
+// would leave these bounds sets the overflow flag, and the caller keeps the
+// LLL basis.
 constexpr long long kGramMax = 1ll << 52;
 
 struct Bkz {
