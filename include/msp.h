@@ -118,6 +118,22 @@ typedef struct {
     int disc_count;       /* reading of a discrepancy (Section 3): 0 = a value's
                            * rank in its level's value order, 1 = one for every
                            * value other than the level's first              [0] */
+    int64_t root_begin;   /* MSP_ALL / MSP_FIRST: walk only the subtree roots at
+                           * positions root_begin .. root_begin + root_count - 1
+                           * of the walk order (depth-first, or the root order's
+                           * ranking), clipped to the roots there are.  Subtrees
+                           * are independent, so the solution sets of disjoint
+                           * ranges are disjoint, their union over a cover of the
+                           * roots is the full set, and their counters add up to
+                           * the full walk's (the levels above the split are
+                           * counted by the call whose range starts at 0 only):
+                           * a caller can checkpoint at a root
+                           * position and resume there, or split the roots over
+                           * several devices.  The split must be the same in
+                           * every call (split_depth >= 0, or the same automatic
+                           * split: same instance, basis and parameters).  Not
+                           * with MSP_LDS or refinement (MSP_E_ARG).            [0] */
+    int64_t root_count;   /* roots in the range; -1 = all from root_begin        [-1] */
 } msp_params;
 
 /* Counters and timings of one call (all times in milliseconds).

@@ -61,7 +61,7 @@ class Params(C.Structure):
         ("hoelder", C.c_int), ("onedir", C.c_int), ("time_cap_ms", C.c_double),
         ("refine", C.c_int), ("refine_keep", C.c_int), ("disc_budget", C.c_int),
         ("bkz_block", C.c_int), ("bkz_tours", C.c_int), ("restarts", C.c_int), ("restart_seed", C.c_uint32),
-        ("disc_count", C.c_int),
+        ("disc_count", C.c_int), ("root_begin", C.c_int64), ("root_count", C.c_int64),
     ]
 
 

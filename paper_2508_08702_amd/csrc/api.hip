@@ -210,6 +210,8 @@ int msp_params_default(msp_params *p) {
     p->restarts = 1;
     p->restart_seed = 1;
     p->disc_count = 0;
+    p->root_begin = 0;
+    p->root_count = -1;
     return MSP_OK;
 }
 
@@ -343,6 +345,8 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     if (!(p.eps >= 0.0) || p.split_depth < -1 || p.split_depth > k - 1) return MSP_E_ARG;
     if (p.refine < -1 || p.refine_keep < 0 || p.target_roots < 0 || p.disc_budget > 255) return MSP_E_ARG;
     if (p.disc_count != 0 && p.disc_count != 1) return MSP_E_ARG;
+    if (p.root_begin < 0 || p.root_count < -1) return MSP_E_ARG;
+    const bool ranged = p.root_begin != 0 || p.root_count >= 0;
     *n_found = 0;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
@@ -537,8 +541,8 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
                 tb = c->sort_tmp.cap;
                 MSP_TRY(sort_idx_asc(c->sort_tmp.p, &tb, c->order.as<int64_t>(), c->top_idx.as<int64_t>(), keep, st));
                 const int nxt = (cur + 1) % 3, oth = (cur + 2) % 3;
-                MSP_TRY(launch_gather_frontier(c->fr[cur].view(), c->top_idx.as<int64_t>(), keep, c->fr[nxt].view(), k,
-                                               ws, st));
+                MSP_TRY(launch_gather_frontier(c->fr[cur].view(), c->top_idx.as<int64_t>(), 0, keep, c->fr[nxt].view(),
+                                               k, ws, st));
                 int a = nxt;
                 int64_t n2 = keep;
                 int L2 = L;
@@ -560,6 +564,26 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     }
     const bool use_order = ordered && np > 1;
 
+    // ---- optional range of root positions (checkpoint / resume, sharding):
+    // the records at those positions of the walk order, gathered into fr[2] ----
+    int wcur = cur;            // frontier holding the walked roots
+    int64_t wnp = np;          // walked roots
+    const int64_t *worder = use_order ? c->order.as<int64_t>() : nullptr;
+    if (ranged) {
+        if (refine) return MSP_E_ARG;
+        const int64_t rb = std::min<int64_t>(p.root_begin, np);
+        const int64_t rn = p.root_count < 0 ? np - rb : std::min<int64_t>(p.root_count, np - rb);
+        MSP_TRY(c->fr[2].ensure(fcap, k, ws));
+        MSP_TRY(launch_gather_frontier(c->fr[cur].view(), worder ? worder + rb : nullptr, rb, rn, c->fr[2].view(), k,
+                                       ws, st));
+        wcur = 2;
+        wnp = rn;
+        worder = nullptr;
+        // only the call whose range starts at position 0 counts the levels
+        // above the split, so the counters of a cover of the roots add up
+        if (p.root_begin > 0) MSP_TRY(launch_fill_int(reinterpret_cast<int *>(ctl->counters), 16, 0, st));
+    }
+
     // ---- subtree walk (levels L0-1 .. 0) ----
     int wblock = walk_block_for(dimp, k, L0);
     if (p.block != 0 && wblock != 0) wblock = std::min(wblock, p.block);
@@ -574,7 +598,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     const int64_t nwalk = (int64_t)c->num_cus * wblock;
     MSP_TRY(c->stack.ensure((size_t)nwalk * k * 4 * sizeof(double)));
     MSP_TRY(c->leaf_x.ensure((size_t)nwalk * n));
-    const int64_t ninit = np + nleft;  // roots with stored w, then prefix-only items
+    const int64_t ninit = wnp + nleft;  // roots with stored w, then prefix-only items
     const int64_t pcap = ninit + std::max<int64_t>(256 * nwalk, 1 << 22);
     if (pcap + nwalk >= (int64_t(1) << 31)) return MSP_E_UNSUPPORTED;  // walker tickets are 32-bit
     MSP_TRY(c->pool_u.ensure((size_t)pcap * k));
@@ -582,7 +606,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));
     Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), pcap};
     if (ninit > 0) {
-        MSP_TRY(launch_pool_init(c->fr[cur].view(), np, k, L, pool, st));
+        MSP_TRY(launch_pool_init(c->fr[wcur].view(), wnp, k, L, pool, st));
         // leftovers of the refinement stages, latest stage first
         int64_t pos = np;
         for (size_t s = left.size(); s-- > 0;) {
@@ -613,11 +637,11 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.A = A_dev;
         wa.d = d_dev;
         wa.pool = pool;
-        wa.nroots = np;
-        wa.root_w = c->fr[cur].w.as<double>();
-        wa.root_wcap = c->fr[cur].cap;
-        wa.root_l = c->fr[cur].l.as<double>();
-        wa.order = use_order ? c->order.as<int64_t>() : nullptr;
+        wa.nroots = wnp;
+        wa.root_w = c->fr[wcur].w.as<double>();
+        wa.root_wcap = c->fr[wcur].cap;
+        wa.root_l = c->fr[wcur].l.as<double>();
+        wa.order = worder;
         wa.sol_u = sol_u;
         wa.head = &ctl->qhead;
         wa.tail = &ctl->qtail;
@@ -645,7 +669,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         MSP_TRY(hipEventRecord(c->ev[4], st));
         int grid = c->num_cus;
         if (small_tree && nleft == 0)
-            grid = (int)std::min<int64_t>(c->num_cus, std::max<int64_t>(1, (2 * np + wblock - 1) / wblock));
+            grid = (int)std::min<int64_t>(c->num_cus, std::max<int64_t>(1, (2 * wnp + wblock - 1) / wblock));
         MSP_TRY(launch_walk(wa, dimp, wblock, grid, st));
         MSP_TRY(hipEventRecord(c->ev[5], st));
     } else {
@@ -700,6 +724,7 @@ static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int6
     msp_params_default(&p);
     if (pin) p = *pin;
     if (!n_found) return MSP_E_ARG;
+    if (p.root_begin != 0 || p.root_count >= 0) return MSP_E_ARG;  // root positions change from pass to pass
     msp_stats acc;
     std::memset(&acc, 0, sizeof(acc));
     acc.ttfs_ms = -1.0;
@@ -913,6 +938,7 @@ int msp_solve_first(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_
     msp_params_default(&p);
     if (pin) p = *pin;
     if (p.restarts < 1 || p.restarts > 64) return MSP_E_ARG;
+    if (p.root_begin != 0 || p.root_count >= 0) return MSP_E_ARG;
     if (p.N < 1 || !(p.delta > 0.25 && p.delta < 1.0)) return MSP_E_ARG;
     if (p.bkz_block < 0 || p.bkz_block == 1 || p.bkz_block > 40) return MSP_E_ARG;
     *n_found = 0;

@@ -138,8 +138,9 @@ int walk_block_for(int dimp, int k, int L);  // 0 when no variant fits
 int walk_max_level(int dimp, int k);         // largest split level whose walker fits in LDS
 
 hipError_t launch_pool_init(Frontier f, int64_t nroots, int k, int L, Pool pool, hipStream_t st);
-hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws,
-                                  hipStream_t st);
+// dst record r = src record idx[r] (idx == nullptr: base + r), r < n
+hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t base, int64_t n, Frontier dst, int k,
+                                  int ws, hipStream_t st);
 hipError_t launch_frontier_items(Frontier src, const int64_t *idx, int64_t n, int k, int L, int8_t *iu, int4 *imeta,
                                  hipStream_t st);
 hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);

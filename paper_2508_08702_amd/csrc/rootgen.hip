@@ -126,11 +126,12 @@ __global__ void pool_init_kernel(Frontier f, int64_t nroots, int k, int L, Pool 
 }
 
 // Copy frontier records idx[0..n) of src into dst[0..n) (one wave per record).
-__global__ void gather_frontier_kernel(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws) {
+__global__ void gather_frontier_kernel(Frontier src, const int64_t *idx, int64_t base, int64_t n, Frontier dst, int k,
+                                       int ws) {
     const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
     if (r >= n) return;
-    const int64_t s = idx[r];
+    const int64_t s = idx ? idx[r] : base + r;
     for (int j = lane; j < ws; j += 64) dst.w[(size_t)j * dst.wcap + r] = src.w[(size_t)j * src.wcap + s];
     for (int j = lane; j < k; j += 64) dst.u[r * k + j] = src.u[s * k + j];
     if (lane == 0) {
@@ -158,11 +159,11 @@ __global__ void fill_int_kernel(int *p, int64_t n, int v) {
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t n, Frontier dst, int k, int ws,
-                                  hipStream_t st) {
+hipError_t launch_gather_frontier(Frontier src, const int64_t *idx, int64_t base, int64_t n, Frontier dst, int k,
+                                  int ws, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_frontier_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, src, idx, n, dst, k,
-                       ws);
+    hipLaunchKernelGGL(gather_frontier_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, src, idx, base, n, dst,
+                       k, ws);
     return hipGetLastError();
 }
 

@@ -212,3 +212,41 @@ def test_cornuejols_dawande_instances(M, ctx, seed):
     r2 = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(time_cap_ms=60000.0))
     assert r2.status == M.MSP_OK
     assert np.array_equal(E.sort_rows(r2.x.cpu().numpy()), ref.solutions)
+
+
+@pytest.mark.parametrize("m,n,D,seed,order", [(4, 30, 20, 7, 0), (7, 60, 100, 4100, 0), (5, 40, 10, 3, 2)])
+def test_root_ranges_partition_the_walk(M, ctx, m, n, D, seed, order):
+    """Walking the roots in three disjoint position ranges (a checkpoint and
+    two resumptions) gives disjoint solution sets whose union is the full set,
+    and counters that add up to the full walk's; a range past the last root
+    walks nothing.  In depth-first and in learned root order."""
+    inst = mi.planted(m, n, D, seed)
+    P = L.prepare(inst.A, inst.d)
+    if order == 2:
+        M.msp_model_init(ctx, 5)
+    A, d, Bk = _dev(inst.A), _dev(inst.d), _dev(P.basis)
+    full = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(time_cap_ms=60000.0), order=order,
+                           cap=1 << 16)
+    assert full.status == M.MSP_OK and full.stats["roots"] >= 3
+    np_ = full.stats["roots"]
+    cuts = [0, np_ // 3, 2 * np_ // 3, np_]
+    xs, tot = [], {key: 0 for key in ("evals", "nodes", "expansions", "leaves")}
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        prm = M.msp_params_default(time_cap_ms=60000.0, root_begin=a, root_count=(b - a if b < np_ else -1))
+        r = M.msp_enumerate(ctx, A, d, Bk, params=prm, order=order, cap=1 << 16)
+        assert r.status == M.MSP_OK and r.stats["roots"] == np_ and r.stats["initial_items"] == b - a
+        xs.append(E.sort_rows(r.x.cpu().numpy()))
+        for key in tot:
+            tot[key] += r.stats[key]
+    allx = np.concatenate(xs) if sum(len(x) for x in xs) else np.zeros((0, n), np.uint8)
+    assert len(allx) == full.n_found == len({bytes(row) for row in allx})       # disjoint
+    assert np.array_equal(E.sort_rows(allx), E.sort_rows(full.x.cpu().numpy()))
+    assert np.array_equal(E.sort_rows(full.x.cpu().numpy()), E.solve(inst.A, inst.d)[1].solutions)
+    for key in tot:
+        assert tot[key] == full.stats[key], key
+    past = M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(root_begin=np_ + 5), order=order)
+    assert past.status == M.MSP_OK and past.n_found == 0 and past.stats["initial_items"] == 0
+    with pytest.raises(M.MspError):
+        M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(root_begin=-1))
+    with pytest.raises(M.MspError):
+        M.msp_enumerate(ctx, A, d, Bk, params=M.msp_params_default(root_count=5), mode=M.MSP_LDS)
