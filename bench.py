@@ -46,8 +46,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
 # valid only for the kernel source they were taken on.
 WALK_TRAFFIC = {
-    ("m9-1", 0): {"bytes": 1.367e13,
-                  "sha256": "b0c6ee8ac6b9047cdaa670f13a628d0cca1bd827fdce045aeca22ec3204a572e",
+    ("m9-1", 0): {"bytes": 1.365e13,
+                  "sha256": "8126b85ad63861564d4b3a0cb09f46a0e17704f8a798238999d50d473136d9bd",
                   "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
 }
 
