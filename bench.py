@@ -49,6 +49,9 @@ WALK_TRAFFIC = {
     ("m9-1", 0): {"bytes": 1.365e13,
                   "sha256": "8126b85ad63861564d4b3a0cb09f46a0e17704f8a798238999d50d473136d9bd",
                   "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
+    ("m11-b10", 16): {"bytes": 1.280e13,
+                      "sha256": "8126b85ad63861564d4b3a0cb09f46a0e17704f8a798238999d50d473136d9bd",
+                      "profile": "profiles/walk_kernel_m11_n100_bkz16_seed5003_budget10.md"},
 }
 
 
@@ -73,6 +76,11 @@ WORKLOADS = {
     "cd8": ("4 Cornuejols-Dawande instances m=8, n=70, D=100, d = floor(row sums / 2) "
             "(seeds 6000-6003), exhaustive (mostly infeasible: empty output after the full walk)",
             [(8, 100, 6000 + i) for i in range(4)], "cd"),
+    # the walker variant of the m=11 first-solution passes (one wave per SIMD, budget state),
+    # exhaustive within one discrepancy budget on a BKZ-16 basis; extra parameters in the dict
+    "m11-b10": ("1 planted instance m=11, n=100, D=50 (seed 5003), BKZ-16 basis, every path with at most "
+                "10 discrepancies (rank reading)",
+                [(11, 50, 5003)], "planted", {"bkz_block": 16, "disc_budget": 10}),
 }
 
 
@@ -265,7 +273,8 @@ def main():
     import msp_instances as mi
     import paper_2508_08702_amd as M
 
-    desc, spec, gen = WORKLOADS[args.workload]
+    desc, spec, gen = WORKLOADS[args.workload][:3]
+    extra = WORKLOADS[args.workload][3] if len(WORKLOADS[args.workload]) > 3 else {}
     if gen == "cd":
         insts = [mi.cornuejols_dawande(m, s, D) for (m, D, s) in spec]
     else:
@@ -274,6 +283,8 @@ def main():
     dev_in = [(torch.from_numpy(i.A).to(dev), torch.from_numpy(i.d).to(dev)) for i in insts]
     ctx = M.Context(0)
     prm = M.msp_params_default(time_cap_ms=args.time_cap_ms, bkz_block=args.bkz)
+    for key, val in extra.items():
+        setattr(prm, key, val)
     out = torch.zeros((1 << 16, max(i.n for i in insts)), dtype=torch.uint8, device=dev)
 
     def step(record):
@@ -325,7 +336,7 @@ def main():
         flops += st["nodes"] * (3 * dim + 4) + (st["evals"] - st["nodes"]) * 4
         kern_s += st["kernel_ms"] * 1e-3
     achieved = flops / kern_s / 1e12 if kern_s > 0 else 0.0
-    tr = WALK_TRAFFIC.get((args.workload, args.bkz))
+    tr = WALK_TRAFFIC.get((args.workload, prm.bkz_block))
     traffic = tr["bytes"] if tr and tr["sha256"] == walk_source_hash() else None
     res = {
         "metric": "enum nodes/s + time-to-first-solution, m=9..11, plain vs learned order",
@@ -341,7 +352,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "mode": "all", "order": "plain",
-                   "reduction": f"BKZ-{args.bkz}" if args.bkz else "LLL",
+                   "reduction": f"BKZ-{prm.bkz_block}" if prm.bkz_block else "LLL",
+                   **({"disc_budget": prm.disc_budget} if "disc_budget" in extra else {}),
                    "nodes_per_step": nodes // max(1, args.steps)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
