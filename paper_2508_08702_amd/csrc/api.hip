@@ -332,7 +332,7 @@ int msp_gram_schmidt(msp_ctx *c, int k, int dim, const int64_t *basis_dev, doubl
 static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const int64_t *d_dev,
                           const int64_t *basis_dev, int k, int mode, int order, const msp_params *pin, uint8_t *x_dev,
                           int64_t cap, int64_t *n_found, msp_stats *stats, void *stream, int8_t *sol_u = nullptr,
-                          const int64_t *cvec = nullptr, long long rmax = 1) {
+                          const int64_t *cvec = nullptr, long long rmax = 1, bool gs_ready = false) {
     auto t_call = std::chrono::steady_clock::now();
     if (!c || !A_dev || !d_dev || !basis_dev || !n_found || (cap > 0 && !x_dev) || cap < 0) return MSP_E_ARG;
     if (m < 1 || n < 1 || m > n || n > MSP_MAX_N || k != n - m + 1) return MSP_E_ARG;
@@ -363,14 +363,20 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     Ctl *ctl = c->ctl.as<Ctl>();
     MSP_TRY(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
     MSP_TRY(hipEventRecord(c->ev[0], st));
-    GsArgs ga{k, dim, basis_dev, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->gs_beta.as<double>(),
-              &ctl->gs_err};
-    MSP_TRY(launch_gram_schmidt(ga, st));
+    // gs_ready: the caller ran this call's Gram-Schmidt on the same basis
+    // before (the passes of one discrepancy search), and the buffers hold it
+    if (!gs_ready) {
+        GsArgs ga{k, dim, basis_dev, c->gs_bhat.as<double>(), c->gs_mu.as<double>(), c->gs_beta.as<double>(),
+                  &ctl->gs_err};
+        MSP_TRY(launch_gram_schmidt(ga, st));
+    }
     MSP_TRY(hipEventRecord(c->ev[1], st));
-    int gs_err = 0;
-    MSP_TRY(hipMemcpyAsync(&gs_err, &ctl->gs_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    MSP_TRY(hipStreamSynchronize(st));
-    if (gs_err) return MSP_E_NUMERIC;
+    if (!gs_ready) {
+        int gs_err = 0;
+        MSP_TRY(hipMemcpyAsync(&gs_err, &ctl->gs_err, sizeof(int), hipMemcpyDeviceToHost, st));
+        MSP_TRY(hipStreamSynchronize(st));
+        if (gs_err) return MSP_E_NUMERIC;
+    }
 
     const double R = (double)(n + 1) * (double)rmax * (double)rmax;  // (n+1) r_max^2 (Algorithm 1, step 4)
     const double bound = R * (1.0 + p.eps);
@@ -751,7 +757,7 @@ static int lds_search(msp_ctx *c, int m, int n, const int32_t *A_dev, const int6
         const double before =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         rc = enumerate_impl(c, m, n, A_dev, d_dev, basis_dev, k, MSP_FIRST, order, &q, x_dev, cap, n_found, &st,
-                            stream, nullptr, cvec, rmax);
+                            stream, nullptr, cvec, rmax, passes > 0);
         ++passes;
         acc.evals += st.evals;
         acc.nodes += st.nodes;

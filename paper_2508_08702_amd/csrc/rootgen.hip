@@ -17,25 +17,77 @@
 
 namespace msp {
 
+namespace {
+
+// A thread works alone on its parent, so every loop below issues the loads of
+// kChunk elements before it uses any of them: one memory round trip per chunk
+// instead of one per element.  The loads are unconditional (an index past the
+// end is clamped to the last element, whose value is then not used), so the
+// compiler needs no branch, and no wait, per element.  Each sum keeps its
+// element order, so results are bit-identical to the plain loops.
+constexpr int kChunk = 16;
+
+// centre_natural's sum (term p = k-1-i into partial sum p mod 4, fused
+// multiply-adds in increasing p), with batched loads
+__device__ __forceinline__ double centre_batched(const int8_t *__restrict__ u, const double *__restrict__ mu, int k,
+                                                 int t) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nt = k - 1 - t;
+    for (int p0 = 0; p0 < nt; p0 += kChunk) {
+        double uv[kChunk], mv[kChunk];
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r) {
+            const int p = p0 + r < nt ? p0 + r : nt - 1, i = k - 1 - p;
+            uv[r] = (double)u[i];
+            mv[r] = mu[(size_t)i * k + t];
+        }
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r)
+            if (p0 + r < nt) s[r & 3] = fma(uv[r], mv[r], s[r & 3]);
+    }
+    return combine4(s[0], s[1], s[2], s[3]);
+}
+
+// sum_j |x b_t[j] + w[j]| over j = 0 .. dim-1 in increasing j
+__device__ __forceinline__ double l1_batched(double x, const double *__restrict__ bt, const double *__restrict__ wp,
+                                             int64_t pw, int dim) {
+    double h = 0.0;
+    for (int j0 = 0; j0 < dim; j0 += kChunk) {
+        double pv[kChunk], bv[kChunk];
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r) {
+            const int j = j0 + r < dim ? j0 + r : dim - 1;
+            pv[r] = wp[(size_t)j * pw];
+            bv[r] = bt[j];
+        }
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r)
+            if (j0 + r < dim) h += fabs(fma(x, bv[r], pv[r]));
+    }
+    return h;
+}
+
+}  // namespace
+
 template <bool WRITE>
 __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ce = 0, cn = 0, cx = 0;
     if (p < a.np) {
         const int k = a.k, dim = a.dim, t = a.t;
-        const int8_t *up = a.par.u + p * k;
-        const double *wp = a.par.w + p;  // column-major: element j at wp[j * pw]
+        const int8_t *__restrict__ up = a.par.u + p * k;
+        const double *__restrict__ wp = a.par.w + p;  // column-major: element j at wp[j * pw]
         const int64_t pw = a.par.wcap;
         const double lpar = a.par.l[p];
         const bool tz = a.par.tz[p] != 0;
         const int pd = a.par.dsc[p];
-        const double y = centre_natural(up, a.mu, k, t);
+        const double y = centre_batched(up, a.mu, k, t);
         const Zig z = zig_init(y, tz);
         int u = z.u1;
         bool onedir = tz;
         int dir = 1;
         const double beta = a.beta[t];
-        const double *bt = a.bhat + (size_t)t * dim;
+        const double *__restrict__ bt = a.bhat + (size_t)t * dim;
         int64_t slot = WRITE ? a.offs[p] : 0;
         int64_t nch = 0;
         for (;;) {
@@ -50,8 +102,7 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
             ++cn;
             bool fail = false;
             if (a.hoelder) {
-                double h = 0.0;
-                for (int j = 0; j < dim; ++j) h += fabs(fma(x, bt[j], wp[(size_t)j * pw]));
+                const double h = l1_batched(x, bt, wp, pw, dim);
                 fail = l > (a.rmax * h) * a.hfac;
             }
             if (fail) {
@@ -66,12 +117,35 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
                 ++cx;
                 if (WRITE) {
                     if (u > 127 || u < -127) atomicOr(&a.flags[1], 1);
-                    int8_t *uc = a.ch.u + slot * k;
-                    for (int i = 0; i < k; ++i) uc[i] = i > t ? up[i] : (i == t ? (int8_t)u : (int8_t)0);
-                    double *wc = a.ch.w + slot;
+                    int8_t *__restrict__ uc = a.ch.u + slot * k;
+                    for (int i0 = 0; i0 < k; i0 += kChunk) {
+                        int8_t v[kChunk];
+#pragma unroll
+                        for (int r = 0; r < kChunk; ++r) {
+                            v[r] = up[i0 + r < k ? i0 + r : k - 1];
+                        }
+#pragma unroll
+                        for (int r = 0; r < kChunk; ++r) {
+                            const int i = i0 + r;
+                            if (i < k) uc[i] = i > t ? v[r] : (i == t ? (int8_t)u : (int8_t)0);
+                        }
+                    }
+                    double *__restrict__ wc = a.ch.w + slot;
                     const int64_t cw = a.ch.wcap;
-                    for (int j = 0; j < a.dimp; ++j)
-                        wc[(size_t)j * cw] = j < dim ? fma(x, bt[j], wp[(size_t)j * pw]) : 0.0;
+                    for (int j0 = 0; j0 < a.dimp; j0 += kChunk) {
+                        double pv[kChunk], bv[kChunk];
+#pragma unroll
+                        for (int r = 0; r < kChunk; ++r) {
+                            const int j = j0 + r < dim ? j0 + r : dim - 1;
+                            pv[r] = wp[(size_t)j * pw];
+                            bv[r] = bt[j];
+                        }
+#pragma unroll
+                        for (int r = 0; r < kChunk; ++r) {
+                            const int j = j0 + r;
+                            if (j < a.dimp) wc[(size_t)j * cw] = j < dim ? fma(x, bv[r], pv[r]) : 0.0;
+                        }
+                    }
                     a.ch.l[slot] = l;
                     a.ch.tz[slot] = (tz && u == 0) ? 1 : 0;
                     a.ch.dsc[slot] = (uint8_t)(pd + rank < 255 ? pd + rank : 255);
