@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/msp.h"
+#include "expand_thin.h"
 #include "msp_internal.h"
 
 using namespace msp;
@@ -110,6 +111,7 @@ struct Ctl {
     int gs_err;
     int pad;
     int64_t total;
+    ThinOut thin;
 };
 
 }  // namespace
@@ -416,35 +418,66 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     if (L_fit < 1) return MSP_E_UNSUPPORTED;
 
     // Expand the frontier in fr[cur] (np nodes of level L) one level at a
-    // time into fr[other], swapping, until done(np, L) or level 1.  A level
-    // that would not fit the frontier buffers is not taken.
+    // time into fr[other], swapping, until the rule says done or level 1.  A
+    // level that would not fit the frontier buffers is not taken.  While a
+    // level has at most kThinMax parents, one launch takes the levels (one
+    // host round trip for all of them); wider levels take a count launch,
+    // a scan, a host read of the total and a write launch each.
     bool capped = false;  // a level was left unexpanded for lack of frontier room
-    auto expand = [&](int &cur, int other, int64_t &np, int &L, auto done) -> int {
-        for (int t = L - 1; t >= 1; --t) {
-            if (done(np, L)) break;
-            ExpandArgs ea{};
-            ea.k = k;
-            ea.dim = dim;
-            ea.dimp = dimp;
-            ea.ws = ws;
+    auto expand = [&](int &cur, int other, int64_t &np, int &L, const ThinRule &rule) -> int {
+        ExpandArgs base{};  // what every level shares
+        base.k = k;
+        base.dim = dim;
+        base.dimp = dimp;
+        base.ws = ws;
+        base.bhat = c->gs_bhat.as<double>();
+        base.mu = c->gs_mu.as<double>();
+        base.beta = c->gs_beta.as<double>();
+        base.offs = c->offs.as<int64_t>();
+        base.counts = c->counts.as<int64_t>();
+        base.bound = bound;
+        base.hfac = hfac;
+        base.rmax = (double)rmax;
+        base.budget = p.disc_budget;
+        base.disc_count = p.disc_count;
+        base.hoelder = p.hoelder;
+        base.onedir = p.onedir;
+        base.counters = ctl->counters;
+        base.flags = ctl->flags;
+        while (L - 1 >= 1 && !thin_done(rule, np, L)) {
+            if (np >= 1 && np <= kThinMax) {
+                ThinArgs ta;
+                std::memset(&ta, 0, sizeof(ta));
+                ta.e = base;
+                ta.fr[0] = c->fr[cur].view();
+                ta.fr[1] = c->fr[other].view();
+                ta.np = np;
+                ta.L = L;
+                ta.fcap = fcap;
+                ta.rule = rule;
+                ta.out = &ctl->thin;
+                MSP_TRY(launch_expand_thin(ta, st));
+                ThinOut o;
+                MSP_TRY(hipMemcpyAsync(&o, &ctl->thin, sizeof(o), hipMemcpyDeviceToHost, st));
+                MSP_TRY(hipStreamSynchronize(st));
+                if (o.cur) std::swap(cur, other);
+                const bool moved = o.L != L;
+                np = o.np;
+                L = o.L;
+                if (o.capped) {
+                    capped = true;
+                    break;
+                }
+                if (np == 0) break;
+                // it stopped at the rule, at level 1 or at a level too wide for it
+                if (moved) continue;
+            }
+            const int t = L - 1;
+            ExpandArgs ea = base;
             ea.t = t;
-            ea.bhat = c->gs_bhat.as<double>();
-            ea.mu = c->gs_mu.as<double>();
-            ea.beta = c->gs_beta.as<double>();
             ea.par = c->fr[cur].view();
             ea.np = np;
             ea.ch = c->fr[other].view();
-            ea.offs = c->offs.as<int64_t>();
-            ea.counts = c->counts.as<int64_t>();
-            ea.bound = bound;
-            ea.hfac = hfac;
-            ea.rmax = (double)rmax;
-            ea.budget = p.disc_budget;
-            ea.disc_count = p.disc_count;
-            ea.hoelder = p.hoelder;
-            ea.onedir = p.onedir;
-            ea.counters = ctl->counters;
-            ea.flags = ctl->flags;
             MSP_TRY(launch_expand_count(ea, st));
             size_t tb = c->scan_tmp.cap;
             MSP_TRY(launch_scan(c->scan_tmp.p, &tb, c->counts.as<int64_t>(), c->offs.as<int64_t>(), np, &ctl->total,
@@ -469,10 +502,17 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     int64_t np = 1;
     int L = k;
     {
-        const bool fixed = p.split_depth >= 0;
-        int rc = expand(cur, 1, np, L, [&](int64_t n_, int L_) {
-            return fixed ? k - L_ >= p.split_depth : (n_ >= target && L_ <= L_fit);
-        });
+        ThinRule rule{};
+        rule.k = k;
+        if (p.split_depth >= 0) {  // fixed split depth
+            rule.kind = 0;
+            rule.depth = p.split_depth;
+        } else {  // enough roots, and deep enough for the walker's LDS rows
+            rule.kind = 1;
+            rule.target = target;
+            rule.lb = L_fit;
+        }
+        int rc = expand(cur, 1, np, L, rule);
         if (rc != MSP_OK) return rc;
     }
     const int L0 = L;  // highest level of any walked item: the walker's LDS rows
@@ -552,7 +592,12 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
                 int a = nxt;
                 int64_t n2 = keep;
                 int L2 = L;
-                rc = expand(a, oth, n2, L2, [&](int64_t n_, int L_) { return n_ >= target || L_ <= L_stop; });
+                ThinRule rule{};
+                rule.kind = 2;  // enough roots, or as deep as the refinement goes
+                rule.k = k;
+                rule.target = target;
+                rule.lb = L_stop;
+                rc = expand(a, oth, n2, L2, rule);
                 if (rc != MSP_OK) return rc;
                 ++stages;
                 const bool deeper = L2 < L;  // false: the next level would not fit the buffers

@@ -13,6 +13,7 @@
 #include <rocprim/device/device_scan.hpp>
 
 #include "enum_rules.h"
+#include "expand_thin.h"
 #include "msp_internal.h"
 
 namespace msp {
@@ -67,13 +68,14 @@ __device__ __forceinline__ double l1_batched(double x, const double *__restrict_
     return h;
 }
 
-}  // namespace
-
+// The level-t rules for parent p: returns its number of children and adds
+// its evaluations, nodes and expansions to ce, cn, cx.  WRITE: the children
+// are stored from slot on.
 template <bool WRITE>
-__global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long ce = 0, cn = 0, cx = 0;
-    if (p < a.np) {
+__device__ __forceinline__ int64_t expand_parent(const ExpandArgs &a, int64_t p, int64_t slot,
+                                                 unsigned long long &ce, unsigned long long &cn,
+                                                 unsigned long long &cx) {
+    {
         const int k = a.k, dim = a.dim, t = a.t;
         const int8_t *__restrict__ up = a.par.u + p * k;
         const double *__restrict__ wp = a.par.w + p;  // column-major: element j at wp[j * pw]
@@ -88,7 +90,6 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
         int dir = 1;
         const double beta = a.beta[t];
         const double *__restrict__ bt = a.bhat + (size_t)t * dim;
-        int64_t slot = WRITE ? a.offs[p] : 0;
         int64_t nch = 0;
         for (;;) {
             // a budget stops the level at the first value whose cost would
@@ -155,20 +156,114 @@ __global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
             }
             u = onedir ? u + dir : zig_next(z, u);
         }
+        return nch;
+    }
+}
+
+// Wave sums of the counters, one atomic add each per wave.
+__device__ __forceinline__ void add_counters(unsigned long long *counters, unsigned long long ce,
+                                             unsigned long long cn, unsigned long long cx) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        ce += __shfl_xor(ce, o, 64);
+        cn += __shfl_xor(cn, o, 64);
+        cx += __shfl_xor(cx, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && (ce | cn | cx)) {
+        atomicAdd(&counters[0], ce);
+        atomicAdd(&counters[1], cn);
+        atomicAdd(&counters[2], cx);
+    }
+}
+
+}  // namespace
+
+template <bool WRITE>
+__global__ void __launch_bounds__(256) expand_kernel(ExpandArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long ce = 0, cn = 0, cx = 0;
+    if (p < a.np) {
+        const int64_t nch = expand_parent<WRITE>(a, p, WRITE ? a.offs[p] : 0, ce, cn, cx);
         if (!WRITE) a.counts[p] = nch;
     }
-    if (WRITE) {
-        // wave reduction, one atomic per wave
-        for (int o = 32; o >= 1; o >>= 1) {
-            ce += __shfl_xor(ce, o, 64);
-            cn += __shfl_xor(cn, o, 64);
-            cx += __shfl_xor(cx, o, 64);
+    if (WRITE) add_counters(a.counters, ce, cn, cx);
+}
+
+// Thin levels in one launch: one workgroup expands level after level while
+// the parents number at most kThinMax, with the count pass, an exclusive scan
+// of the counts in LDS and the write pass of each level separated by
+// barriers.  It takes the same levels as the per-level launches would (the
+// same stop rule, the same capacity check, children in the same slots), so
+// the frontier and the counters are identical; what it saves is the host
+// round trip and the four launches of every level.  The frontier it ends on
+// is in fr[out->cur].
+__global__ void __launch_bounds__(kThinBlock) expand_thin_kernel(ThinArgs a) {
+    __shared__ int cnt[kThinMax];
+    __shared__ int64_t off[kThinMax];
+    __shared__ int64_t wsum[kThinBlock / 64];
+    __shared__ int64_t total_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t np = a.np;
+    int L = a.L, cur = 0, capped = 0;
+    unsigned long long ce = 0, cn = 0, cx = 0;
+    while (L - 1 >= 1 && np <= kThinMax && !thin_done(a.rule, np, L)) {
+        ExpandArgs e = a.e;
+        e.t = L - 1;
+        e.par = a.fr[cur];
+        e.ch = a.fr[cur ^ 1];
+        e.np = np;
+        unsigned long long de = 0, dn = 0, dx = 0;  // the count pass adds no counters
+        for (int64_t p = tid; p < np; p += kThinBlock) cnt[p] = (int)expand_parent<false>(e, p, 0, de, dn, dx);
+        __syncthreads();
+        // exclusive scan: thread tid owns cnt[tid * kThinPer ..] (kThinPer entries)
+        int64_t own = 0;
+        for (int i = 0; i < kThinPer; ++i) {
+            const int64_t q = (int64_t)tid * kThinPer + i;
+            if (q < np) own += cnt[q];
         }
-        if ((threadIdx.x & 63) == 0 && (ce | cn | cx)) {
-            atomicAdd(&a.counters[0], ce);
-            atomicAdd(&a.counters[1], cn);
-            atomicAdd(&a.counters[2], cx);
+        int64_t x = own;  // inclusive sum over the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t acc = 0;
+            for (int w = 0; w < kThinBlock / 64; ++w) {
+                const int64_t v = wsum[w];
+                wsum[w] = acc;
+                acc += v;
+            }
+            total_s = acc;
+        }
+        __syncthreads();
+        int64_t base = wsum[wave] + x - own;
+        for (int i = 0; i < kThinPer; ++i) {
+            const int64_t q = (int64_t)tid * kThinPer + i;
+            if (q < np) {
+                off[q] = base;
+                base += cnt[q];
+            }
+        }
+        const int64_t total = total_s;
+        __syncthreads();
+        if (total > a.fcap) {  // this level would not fit the frontier buffers
+            capped = 1;
+            break;
+        }
+        for (int64_t p = tid; p < np; p += kThinBlock) expand_parent<true>(e, p, off[p], ce, cn, cx);
+        __syncthreads();  // the children are the next level's parents
+        cur ^= 1;
+        np = total;
+        L = e.t;
+        if (np == 0) break;
+    }
+    add_counters(a.e.counters, ce, cn, cx);
+    if (tid == 0) {
+        a.out->np = np;
+        a.out->L = L;
+        a.out->cur = cur;
+        a.out->capped = capped;
     }
 }
 
@@ -263,6 +358,12 @@ hipError_t launch_expand_count(const ExpandArgs &a, hipStream_t st) {
 hipError_t launch_expand_write(const ExpandArgs &a, hipStream_t st) {
     if (a.np <= 0) return hipSuccess;
     hipLaunchKernelGGL(expand_kernel<true>, dim3(grid_for(a.np)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_thin(const ThinArgs &a, hipStream_t st) {
+    if (a.np <= 0 || a.np > kThinMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(expand_thin_kernel, dim3(1), dim3(kThinBlock), 0, st, a);
     return hipGetLastError();
 }
 
