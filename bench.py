@@ -46,11 +46,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
 # valid only for the kernel source they were taken on.
 WALK_TRAFFIC = {
-    ("m9-1", 0): {"bytes": 1.365e13,
-                  "sha256": "8126b85ad63861564d4b3a0cb09f46a0e17704f8a798238999d50d473136d9bd",
+    ("m9-1", 0): {"bytes": 1.367e13,
+                  "sha256": "7a9da6ba44c1213a7af8cf11ba7320f457fa498cfe38bf0516feb84369fcac48",
                   "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
     ("m11-b10", 16): {"bytes": 1.280e13,
-                      "sha256": "8126b85ad63861564d4b3a0cb09f46a0e17704f8a798238999d50d473136d9bd",
+                      "sha256": "7a9da6ba44c1213a7af8cf11ba7320f457fa498cfe38bf0516feb84369fcac48",
                       "profile": "profiles/walk_kernel_m11_n100_bkz16_seed5003_budget10.md"},
 }
 

@@ -65,8 +65,12 @@ __host__ __device__ constexpr int row_stride(int dimp, bool two_wave) {
 
 __device__ __forceinline__ unsigned long long wall_clock() { return wall_clock64(); }
 
-__device__ __forceinline__ int ld_acq(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Flags are polled with relaxed loads.  An acquire load at agent scope also
+// invalidates the wave's caches (the L2 of its XCD included), and the rare-work
+// pass polls every few iterations, so the one flag whose data a lane then
+// reads (a donated pool slot) is followed by a single acquire fence instead.
+__device__ __forceinline__ int ld_rlx(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned long long ld_rlx(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -283,7 +287,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
         {
             int stop = 0;
             if (lane == 0) {
-                stop = ld_acq(&a.flags[0]);
+                stop = ld_rlx(&a.flags[0]);  // guards no data
                 if (!stop && a.deadline) {
                     const unsigned long long t0 = ld_rlx(a.t_start);
                     if (t0 && wall_clock() > t0 + a.deadline) {
@@ -451,10 +455,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 if ((long long)ticket < a.nroots) {
                     take = true;
                 } else {
-                    take = (long long)ticket < a.pool.cap && ld_acq(&a.pool.ready[ticket]) != 0;
+                    take = (long long)ticket < a.pool.cap && ld_rlx(&a.pool.ready[ticket]) != 0;
                     if (!take && ld_rlx(a.pending) == 0) state = DONE;
                 }
             }
+            // a donated slot seen ready: synchronise with its release store
+            // before reading it (once per wave)
+            if (__ballot(take && (long long)ticket >= a.nroots)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             // Item set-up.  w is only ever changed by code that every lane of
             // the wave runs (with a zero coefficient where a lane has nothing
             // to add), never inside a branch that lanes take apart.
