@@ -128,7 +128,7 @@ struct msp_ctx {
     Buf order;
     Buf lll_desc, lll_work, batch_basis;
     Buf g_bh, g_muc, g_coff;
-    Buf pool_u, pool_meta, pool_ready;
+    Buf pool_u, pool_meta, pool_ready, pool_root;
     Buf leaf_x;  // the walkers' leaf staging rows
     Buf box_d, box_r, box_basis, box_x, box_st;  // msp_solve_box: shifted problem and its rows
     long long last_lll_iters = 0;
@@ -301,6 +301,7 @@ void msp_ctx_destroy(msp_ctx *c) {
     c->pool_u.release();
     c->pool_meta.release();
     c->pool_ready.release();
+    c->pool_root.release();
     c->leaf_x.release();
     for (Buf *b : {&c->box_d, &c->box_r, &c->box_basis, &c->box_x, &c->box_st}) b->release();
     for (Buf *b : {&c->feat, &c->key, &c->key_out, &c->idx_in, &c->sort_tmp, &c->scan_tmp, &c->sol_u, &c->trace_x, &c->w_master,
@@ -655,7 +656,9 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
     MSP_TRY(c->pool_u.ensure((size_t)pcap * k));
     MSP_TRY(c->pool_meta.ensure((size_t)pcap * sizeof(int4)));
     MSP_TRY(c->pool_ready.ensure((size_t)pcap * sizeof(int)));
-    Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), pcap};
+    MSP_TRY(c->pool_root.ensure((size_t)pcap * sizeof(int)));
+    Pool pool{c->pool_u.as<int8_t>(), c->pool_meta.as<int4>(), c->pool_ready.as<int>(), c->pool_root.as<int>(),
+              pcap};
     if (ninit > 0) {
         MSP_TRY(launch_pool_init(c->fr[wcur].view(), wnp, k, L, pool, st));
         // leftovers of the refinement stages, latest stage first
@@ -669,6 +672,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
             pos += cnt;
         }
         MSP_TRY(launch_fill_int(pool.ready + np, nleft, 1, st));
+        MSP_TRY(launch_fill_int(pool.root + np, nleft, -1, st));  // no stored root above them
         const unsigned long long qt = (unsigned long long)ninit;
         const long long pend = (long long)ninit;
         MSP_TRY(hipMemcpyAsync(&ctl->qtail, &qt, sizeof(qt), hipMemcpyHostToDevice, st));
@@ -692,6 +696,7 @@ static int enumerate_impl(msp_ctx *c, int m, int n, const int32_t *A_dev, const 
         wa.root_w = c->fr[wcur].w.as<double>();
         wa.root_wcap = c->fr[wcur].cap;
         wa.root_l = c->fr[wcur].l.as<double>();
+        wa.root_level = L;
         wa.order = worder;
         wa.sol_u = sol_u;
         wa.head = &ctl->qhead;

@@ -85,6 +85,7 @@ struct Pool {
     int8_t *u;
     int4 *meta;
     int *ready;
+    int *root;  // donated items: the root they descend from (index into the root arrays), or -1
     int64_t cap;
 };
 
@@ -103,6 +104,7 @@ struct WalkArgs {
     const double *root_w;          // their projected vectors (frontier layout: element j of root r at
     int64_t root_wcap;             //   root_w[j * root_wcap + r], j < DIMP)
     const double *root_l;          // their partial norms
+    int root_level;                // the roots' level: their w includes levels root_level .. k-1
     const int64_t *order;          // optional permutation of those (nullptr = identity)
     unsigned long long *head;      // next ticket
     unsigned long long *tail;      // next free pool slot

@@ -118,6 +118,23 @@ __device__ __forceinline__ double centre_sum(int t, int k, const int8_t *my_u, c
     return combine4(s0, s1, s2, s3);
 }
 
+// A work item's prefix from the pool into the lane's LDS u row: my_u[k-1-j]
+// = pu[j] for j > T, 0 below.  The global loads of 16 bytes are issued before
+// any of them is stored (the index is clamped to the row, so every load is
+// unconditional): one memory round trip per 16 bytes, not per byte.
+__device__ __forceinline__ void load_prefix(int8_t *my_u, const int8_t *__restrict__ pu, int k, int T) {
+    for (int j0 = 0; j0 < k; j0 += 16) {
+        int8_t v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = pu[j0 + r < k ? j0 + r : k - 1];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = j0 + r;
+            if (j < k) my_u[k - 1 - j] = j > T ? v[r] : (int8_t)0;
+        }
+    }
+}
+
 }  // namespace
 
 __host__ __device__ int walk_row_stride(int dimp, int block) { return row_stride(dimp, block == 512); }
@@ -184,8 +201,11 @@ __global__ void walk_prep_kernel(int k, int dim, int dimp, int block, const doub
 // and a lane that takes an item rebuilds the prefix's w with ordinary row
 // updates of the inner loop, one prefix level per iteration (state LOAD),
 // which keeps the rare-work pass small.  Otherwise only rows below the split
-// level are in LDS, and the prefix is rebuilt in the rare-work pass from the
-// rows in HBM (or loaded, for a root that root generation stored).
+// level are in LDS.  A root's w is then loaded as root generation stored it;
+// an item donated below a root starts from that root's stored w and norm (the
+// pool records which root an item descends from) and adds the levels below
+// the roots' level in state LOAD as well; an item with no stored root above it
+// (refinement leftovers) is rebuilt in the rare-work pass from the rows in HBM.
 template <int DIMP, int BLOCK, bool BUDGETED>
 __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     constexpr bool ALLROWS = BLOCK == 512;
@@ -247,6 +267,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
     double Py = 0.0, Pl = 0.0;  // cached state of level t+1: centre and the partial norm above it
     int Pw = 0;                 // u_{t+1} (low byte) | its flags << 8 | dirty << 16 (cache not yet in the stack)
     int dsc = 0, Pdsc = 0;      // discrepancies on the path above level t, and above level t+1
+    int my_root = -1;           // one-wave variant: the stored root the current item descends from
     unsigned c_eval = 0, c_node = 0, c_exp = 0, c_leaf = 0, c_items = 0;  // per lane; wave sums are 64-bit
 
     // add the wave's counters to the global ones (one atomic each) and clear them
@@ -426,6 +447,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                         int8_t *pu = a.pool.u + slot * k;
                         for (int j = 0; j < k; ++j) pu[j] = j > D ? my_u[k - 1 - j] : (int8_t)0;
                         a.pool.meta[slot] = make_int4(D, un, fD & (F_ONEDIR | F_DIRPOS | F_TZ), dD);
+                        if (!ALLROWS) a.pool.root[slot] = my_root;
                         __hip_atomic_store(&a.pool.ready[slot], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         top = D - 1;
                     }
@@ -471,7 +493,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     const int4 mt = a.pool.meta[it];
                     if (BUDGETED) dsc = mt.w;
                     const int8_t *pu = a.pool.u + it * k;
-                    for (int j = 0; j < k; ++j) my_u[k - 1 - j] = j > mt.x ? pu[j] : (int8_t)0;
+                    load_prefix(my_u, pu, k, mt.x);
                     top = mt.x;
                     t = k - 1;          // next prefix level to add
                     lpar = 0.0;         // partial norm of the prefix so far
@@ -484,9 +506,9 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     for (int q = 0; q < DIMP; ++q) w[q] *= keep;
                 }
             } else {
-            long long it = 0;
+            long long it = 0, src = 0;  // src: the root whose stored w and norm the item starts from
             int T = 0, mflags = 0, mstart = 0;
-            bool from_root = false;
+            bool from_root = false, anchored = false;
             if (take) {
                 it = ((long long)ticket < a.nroots && a.order) ? a.order[ticket] : (long long)ticket;
                 const int4 mt = a.pool.meta[it];
@@ -495,17 +517,27 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                 mflags = mt.z;
                 if (BUDGETED) dsc = mt.w;
                 const int8_t *pu = a.pool.u + it * k;
-                for (int j = 0; j < k; ++j) my_u[k - 1 - j] = j > T ? pu[j] : (int8_t)0;
+                load_prefix(my_u, pu, k, T);
                 from_root = it < a.nroots;
+                if (from_root) {
+                    src = it;
+                } else {  // a donated item below a stored root, or one with none above it
+                    const int r = a.pool.root[it];
+                    anchored = r >= 0;
+                    src = anchored ? r : 0;
+                }
+                my_root = (from_root || anchored) ? (int)src : -1;
             }
-            // a root from root generation: w and its norm are stored
-            double l = (take && from_root) ? a.root_l[it] : 0.0;
+            // a root from root generation, or the root a donated item descends
+            // from: w and the partial norm at the roots' level are stored
+            const bool stored = take && (from_root || anchored);
+            double l = stored ? a.root_l[src] : 0.0;
             if (__ballot(take)) {
                 const double keep = take ? 0.0 : 1.0;
-                const double sel = (take && from_root) ? 1.0 : 0.0;
+                const double sel = stored ? 1.0 : 0.0;
                 // register q holds column (rot + q) mod DIMP; the stored vectors
-                // are column-major (a lane without a root reads root 0 and adds 0)
-                const double *pw = a.root_w + ((take && from_root) ? it : 0);
+                // are column-major (a lane without one reads root 0 and adds 0)
+                const double *pw = a.root_w + (stored ? src : 0);
                 const int64_t wc = a.root_wcap;
 #pragma unroll
                 for (int q = 0; q < DIMP; ++q) {
@@ -513,8 +545,13 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     w[q] = fma(sel, pw[(size_t)c * wc], w[q] * keep);
                 }
             }
-            // a prefix-only item: centres, partial norms and w, top level first
-            const bool pref = take && !from_root;
+            // A donated item below a stored root adds the levels between the
+            // roots' level and its own in the inner loop (state LOAD, one level
+            // per iteration, rows in LDS), as the two-wave variant does.  One
+            // with no stored root above it adds its whole prefix here, top
+            // level first.  Either way these are the fused multiply-adds of root
+            // generation in the same order, so w is the same.
+            const bool pref = take && !from_root && !anchored;
             for (int j = k - 1; j >= 1; --j) {
                 const bool act = pref && j > T;
                 if (!__ballot(act)) break;
@@ -524,7 +561,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
                     xj = add_rn((double)my_u[k - 1 - j], yj);
                     l = partial_norm(xj, s_beta[j], l);
                 }
-                const double *gr = a.g_bh + (size_t)j * S + rot;
+                const double *gr = (j < L ? s_bh : a.g_bh) + (size_t)j * S + rot;
 #pragma unroll
                 for (int q = 0; q < DIMP; q += 2) {
                     const double2 b = *reinterpret_cast<const double2 *>(gr + q);
@@ -534,19 +571,25 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             }
             if (take) {
                 lpar = l;
-                t = T;
                 top = T;
-                tz = (mflags & F_TZ) ? 1 : 0;
-                bt = s_beta[T];
-                enter_level();
-                if (!(mflags & F_FRESH)) {
-                    u = mstart;
-                    onedir = mflags & F_ONEDIR;
-                    dir = (mflags & F_DIRPOS) ? 1 : -1;
+                if (anchored && a.root_level - 1 > T) {
+                    t = a.root_level - 1;  // next prefix level to add
+                    Pw = (mstart & 0xFF) | ((mflags & 0xFF) << 8);  // continuation, kept until the level is entered
+                    state = LOAD;
+                } else {
+                    t = T;
+                    tz = (mflags & F_TZ) ? 1 : 0;
+                    bt = s_beta[T];
+                    enter_level();
+                    if (!(mflags & F_FRESH)) {
+                        u = mstart;
+                        onedir = mflags & F_ONEDIR;
+                        dir = (mflags & F_DIRPOS) ? 1 : -1;
+                    }
+                    fex = 0;
+                    Pw = 0;
+                    state = RUN;
                 }
-                fex = 0;
-                Pw = 0;
-                state = RUN;
             }
             }
         }
@@ -563,7 +606,7 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             int row = 0;
             double coef = 0.0;
             bool node = false, popped = false;
-            if (ALLROWS && state == LOAD) {
+            if (state == LOAD) {
                 // one prefix level per iteration, top level first
                 if (t > top) {
                     const double yj = centre_sum(t, k, my_u, s_muc + s_coff[t]);
