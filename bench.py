@@ -46,11 +46,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # 1 GiB device copy in the same run), keyed by (workload, BKZ block size) and
 # valid only for the kernel source they were taken on.
 WALK_TRAFFIC = {
-    ("m9-1", 0): {"bytes": 1.365e13,
-                  "sha256": "96dfdd6c1194d5aa701c762d18dc0a32ceb7d54ae92964b962b19e9a5ec81c98",
+    ("m9-1", 0): {"bytes": 1.367e13,
+                  "sha256": "60b261c0a6ede27a050de03950c128e2c2a0ced6976f462b0f09630c738f295d",
                   "profile": "profiles/walk_kernel_m9_n80_D200_seed4508.md"},
-    ("m11-b10", 16): {"bytes": 1.289e13,
-                      "sha256": "96dfdd6c1194d5aa701c762d18dc0a32ceb7d54ae92964b962b19e9a5ec81c98",
+    ("m11-b10", 16): {"bytes": 1.278e13,
+                      "sha256": "60b261c0a6ede27a050de03950c128e2c2a0ced6976f462b0f09630c738f295d",
                       "profile": "profiles/walk_kernel_m11_n100_bkz16_seed5003_budget10.md"},
 }
 

@@ -532,18 +532,21 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             // from: w and the partial norm at the roots' level are stored
             const bool stored = take && (from_root || anchored);
             double l = stored ? a.root_l[src] : 0.0;
-            if (__ballot(take)) {
-                const double keep = take ? 0.0 : 1.0;
-                const double sel = stored ? 1.0 : 0.0;
-                // register q holds column (rot + q) mod DIMP; the stored vectors
-                // are column-major (a lane without one reads root 0 and adds 0)
-                const double *pw = a.root_w + (stored ? src : 0);
+            // The stored vector goes straight into w's registers: the loads
+            // are written under the lane mask of the lanes that take one, so
+            // they need no other registers and all of them can be in flight
+            // at once.  Column rot + q is at pa + q wc before the wrap and at
+            // pa + (q - DIMP) wc after it (one per-lane pointer, a uniform
+            // stride).
+            if (stored) {
                 const int64_t wc = a.root_wcap;
+                const double *pa = a.root_w + src + (int64_t)rot * wc;
+                const int wrap_at = DIMP - rot;  // first register whose column wraps
 #pragma unroll
-                for (int q = 0; q < DIMP; ++q) {
-                    const int c = rot + q < DIMP ? rot + q : rot + q - DIMP;
-                    w[q] = fma(sel, pw[(size_t)c * wc], w[q] * keep);
-                }
+                for (int q = 0; q < DIMP; ++q) w[q] = pa[(int64_t)(q < wrap_at ? q : q - DIMP) * wc];
+            } else if (take) {
+#pragma unroll
+                for (int q = 0; q < DIMP; ++q) w[q] = 0.0;
             }
             // A donated item below a stored root adds the levels between the
             // roots' level and its own in the inner loop (state LOAD, one level
