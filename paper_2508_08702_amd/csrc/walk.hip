@@ -484,9 +484,11 @@ __global__ void __launch_bounds__(BLOCK) walk_kernel(WalkArgs a) {
             // a donated slot seen ready: synchronise with its release store
             // before reading it (once per wave)
             if (__ballot(take && (long long)ticket >= a.nroots)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // Item set-up.  w is only ever changed by code that every lane of
-            // the wave runs (with a zero coefficient where a lane has nothing
-            // to add), never inside a branch that lanes take apart.
+            // Item set-up.  Row updates of w are made by code that every lane
+            // of the wave runs (with a zero coefficient where a lane has
+            // nothing to add); the one-wave variant's load of a stored w is
+            // the exception, written under the lane mask of the taking lanes
+            // (it needs no registers beyond w's own that way).
             if (ALLROWS) {
                 if (take) {
                     const long long it = ((long long)ticket < a.nroots && a.order) ? a.order[ticket] : (long long)ticket;
