@@ -29,3 +29,24 @@ def test_traffic_figure_matches_its_profile():
         assert tr["sha256"] in txt
         # the profile states the per-launch bytes that bench.py reports
         assert f"{tr['bytes']:.3e}".replace("e+", "e") in txt.replace("e+", "e")
+
+
+def test_traffic_hash_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    """The traffic figure is keyed by the walk kernel's code: editing a comment
+    or a blank line keeps the hash, editing code changes it."""
+    import shutil
+
+    import bench
+    src = os.path.join(ROOT, "paper_2508_08702_amd", "csrc")
+    fake = tmp_path / "paper_2508_08702_amd" / "csrc"
+    fake.mkdir(parents=True)
+    for f in ("walk.hip", "enum_rules.h", "msp_internal.h"):
+        shutil.copy(os.path.join(src, f), fake / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.walk_source_hash()
+    walk = fake / "walk.hip"
+    txt = walk.read_text()
+    walk.write_text(txt.replace("namespace msp {", "// a new comment line\n\nnamespace msp {  /* and a block */", 1))
+    assert bench.walk_source_hash() == h0
+    walk.write_text(txt.replace("namespace msp {", "namespace msp {\nstatic const int unused_marker = 1;", 1))
+    assert bench.walk_source_hash() != h0
