@@ -1,5 +1,7 @@
 // Subtree root generation: the top levels of the enumeration tree, expanded
-// breadth first, one level per launch (tree partitioning, paper Section 4).
+// breadth first (tree partitioning, paper Section 4): a level of more than
+// kThinMax parents per count launch, scan and write launch; runs of smaller
+// levels in one single-workgroup launch (expand_thin_kernel).
 //
 // A level-t launch takes the expanded nodes of level t+1 ("parents", each with
 // its prefix u_{t+1..k-1}, projected vector w^(t+1) and partial norm) and, one
